@@ -1,0 +1,166 @@
+"""wave2d for MI355X: the Poisson-formula explicit schemes for the 2D wave
+equation (Khutoryansky, arXiv:1904.04048) as hand-written gfx950 kernels
+behind a C ABI (include/wave2d.h).
+
+This module is the thin Python binding: each function has the name of the C
+entry point it calls and only marshals arguments.  Grids are torch tensors
+on the GPU of shape (ny, nx) with unit stride along x; the row stride is
+passed as the leading dimension.  Work is enqueued on the current torch
+stream of the tensors' device.
+
+Importing the package does not load the library; the first call does, and
+fails loudly if libwave2d.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (ALLOW_UNSTABLE, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13,
+                   Tuning, Wave2dError)
+
+__all__ = [
+    "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE",
+    "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_work_bytes", "wave2d_first_step",
+    "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_export",
+    "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
+    "wave2d_release",
+]
+
+
+def _grid(*tensors, dtypes):
+    import torch
+    t0 = tensors[0]
+    ny, nx = t0.shape
+    ld = t0.stride(0)
+    dev = t0.device
+    for t, dt in zip(tensors, dtypes):
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("grids must be GPU tensors")
+        if t.dtype != dt:
+            raise ValueError(f"expected {dt}, got {t.dtype}")
+        if t.dim() != 2 or tuple(t.shape) != (ny, nx):
+            raise ValueError("all grids must have the same shape (ny, nx)")
+        if t.stride(1) != 1 or t.stride(0) != ld:
+            raise ValueError("grids need unit x stride and a common row stride")
+        if t.device != dev:
+            raise ValueError("grids on different devices")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    return nx, ny, ld, ctypes.c_void_p(stream)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _work(work):
+    if work is None:
+        return ctypes.c_void_p(0), 0
+    return ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size()
+
+
+def wave2d_lambda_max(scheme: int) -> float:
+    v = _lib.load().wave2d_lambda_max(scheme)
+    if v < 0:
+        raise ValueError(f"unknown scheme {scheme}")
+    return v
+
+
+def wave2d_weights(scheme: int, lam: float, flags: int = 0):
+    """(w2, wa, wb): two-step weights and first-step A / (B/tau) node weights."""
+    w2, wa, wb = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    _lib.check(_lib.load().wave2d_weights(scheme, flags, lam, w2, wa, wb))
+    return list(w2), list(wa), list(wb)
+
+
+def wave2d_work_bytes(precision: int, nx: int, ny: int, ld: int | None = None) -> int:
+    return int(_lib.load().wave2d_work_bytes(precision, nx, ny, nx if ld is None else ld))
+
+
+def wave2d_first_step(u0, v0, u1, h, tau, c, scheme, flags=0):
+    import torch
+    nx, ny, ld, s = _grid(u0, v0, u1, dtypes=(torch.float64,) * 3)
+    _lib.check(_lib.load().wave2d_first_step(nx, ny, ld, h, tau, c, scheme, flags, _p(u0), _p(v0), _p(u1), s))
+
+
+def wave2d_step(u_prev, u_cur, h, tau, c, scheme, steps, flags=0, work=None):
+    import torch
+    nx, ny, ld, s = _grid(u_prev, u_cur, dtypes=(torch.float64,) * 2)
+    wp, wb = _work(work)
+    _lib.check(_lib.load().wave2d_step(nx, ny, ld, h, tau, c, scheme, flags, steps, _p(u_prev), _p(u_cur),
+                                       wp, wb, s))
+
+
+def wave2d_run(u0, v0, u_prev_out, u_out, h, tau, c, scheme, steps, flags=0, work=None):
+    import torch
+    nx, ny, ld, s = _grid(u0, v0, u_prev_out, u_out, dtypes=(torch.float64,) * 4)
+    wp, wb = _work(work)
+    _lib.check(_lib.load().wave2d_run(nx, ny, ld, h, tau, c, scheme, flags, steps, _p(u0), _p(v0),
+                                      _p(u_prev_out), _p(u_out), wp, wb, s))
+
+
+def wave2d_f32c_init(u_prev, u_cur, u, lo, d):
+    import torch
+    nx, ny, ld, s = _grid(u_prev, u_cur, u, lo, d, dtypes=(torch.float64,) * 2 + (torch.float32,) * 3)
+    _lib.check(_lib.load().wave2d_f32c_init(nx, ny, ld, _p(u_prev), _p(u_cur), _p(u), _p(lo), _p(d), s))
+
+
+def wave2d_f32c_step(u, lo, d, h, tau, c, scheme, steps, flags=0, work=None):
+    import torch
+    nx, ny, ld, s = _grid(u, lo, d, dtypes=(torch.float32,) * 3)
+    wp, wb = _work(work)
+    _lib.check(_lib.load().wave2d_f32c_step(nx, ny, ld, h, tau, c, scheme, flags, steps, _p(u), _p(lo), _p(d),
+                                            wp, wb, s))
+
+
+def wave2d_f32c_export(u, lo, out):
+    import torch
+    nx, ny, ld, s = _grid(u, lo, out, dtypes=(torch.float32, torch.float32, torch.float64))
+    _lib.check(_lib.load().wave2d_f32c_export(nx, ny, ld, _p(u), _p(lo), _p(out), s))
+
+
+def wave2d_f32c_run(u0, v0, u, lo, d, h, tau, c, scheme, steps, flags=0, work=None):
+    import torch
+    nx, ny, ld, s = _grid(u0, v0, u, lo, d, dtypes=(torch.float64,) * 2 + (torch.float32,) * 3)
+    wp, wb = _work(work)
+    _lib.check(_lib.load().wave2d_f32c_run(nx, ny, ld, h, tau, c, scheme, flags, steps, _p(u0), _p(v0), _p(u),
+                                           _p(lo), _p(d), wp, wb, s))
+
+
+def wave2d_norms(a, b):
+    """[max|a-b|, max|b|, sum (a-b)^2, sum b^2] (synchronous)."""
+    import torch
+    nx, ny, ld, s = _grid(a, b, dtypes=(torch.float64,) * 2)
+    out = (ctypes.c_double * 4)()
+    _lib.check(_lib.load().wave2d_norms(nx, ny, ld, _p(a), _p(b), out, s))
+    return list(out)
+
+
+def wave2d_f32c_norms(u, lo, b):
+    import torch
+    nx, ny, ld, s = _grid(u, lo, b, dtypes=(torch.float32, torch.float32, torch.float64))
+    out = (ctypes.c_double * 4)()
+    _lib.check(_lib.load().wave2d_f32c_norms(nx, ny, ld, _p(u), _p(lo), _p(b), out, s))
+    return list(out)
+
+
+def wave2d_set_tuning(precision: int, scheme: int, depth: int | None = None, rows: int | None = None):
+    """Override the launch shape for (precision, scheme); no arguments resets it."""
+    L = _lib.load()
+    if depth is None:
+        _lib.check(L.wave2d_set_tuning(precision, scheme, None))
+        return
+    t = Tuning(depth, rows if rows is not None else 64)
+    _lib.check(L.wave2d_set_tuning(precision, scheme, ctypes.byref(t)))
+
+
+def wave2d_get_tuning(precision: int, scheme: int, nx: int = 0, ny: int = 0):
+    t = Tuning()
+    _lib.check(_lib.load().wave2d_get_tuning(precision, scheme, nx, ny, ctypes.byref(t)))
+    return t.depth, t.rows
+
+
+def wave2d_release():
+    _lib.check(_lib.load().wave2d_release())

@@ -1,0 +1,82 @@
+"""ctypes declarations of the C ABI in include/wave2d.h (libwave2d.so)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwave2d.so")
+
+OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+P5, P9, P13, C9 = 5, 9, 13, 109
+FIRST_CONVENTIONAL = 0x1
+ALLOW_UNSTABLE = 0x2
+KERNEL_SIMPLE = 0x100
+F64, F32C = 0, 1
+
+I64 = ctypes.c_int64
+D = ctypes.c_double
+I = ctypes.c_int
+U32 = ctypes.c_uint32
+P = ctypes.c_void_p
+SZ = ctypes.c_size_t
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("rows", ctypes.c_int32)]
+
+
+_SIGS = {
+    "wave2d_lambda_max": (D, [I]),
+    "wave2d_weights": (I, [I, U32, D, P, P, P]),
+    "wave2d_status_str": (ctypes.c_char_p, [I]),
+    "wave2d_last_error": (ctypes.c_char_p, []),
+    "wave2d_work_bytes": (SZ, [I, I64, I64, I64]),
+    "wave2d_first_step": (I, [I64, I64, I64, D, D, D, I, U32, P, P, P, P]),
+    "wave2d_step": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, SZ, P]),
+    "wave2d_run": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P, P, SZ, P]),
+    "wave2d_f32c_init": (I, [I64, I64, I64, P, P, P, P, P, P]),
+    "wave2d_f32c_step": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P, SZ, P]),
+    "wave2d_f32c_export": (I, [I64, I64, I64, P, P, P, P]),
+    "wave2d_f32c_run": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P, P, P, SZ, P]),
+    "wave2d_norms": (I, [I64, I64, I64, P, P, P, P]),
+    "wave2d_f32c_norms": (I, [I64, I64, I64, P, P, P, P, P]),
+    "wave2d_set_tuning": (I, [I, I, P]),
+    "wave2d_get_tuning": (I, [I, I, I64, I64, P]),
+    "wave2d_release": (I, []),
+}
+
+_lib = None
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def load():
+    """Load libwave2d.so.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class Wave2dError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{message} [{status}]")
+
+
+def check(status: int) -> int:
+    if status != OK:
+        L = load()
+        raise Wave2dError(status, f"{L.wave2d_status_str(status).decode()}: {L.wave2d_last_error().decode()}")
+    return status

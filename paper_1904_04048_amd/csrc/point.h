@@ -1,0 +1,100 @@
+// Per-node arithmetic of the schemes, shared by every kernel so that all
+// launch shapes and kernel variants produce bit-identical results.
+//
+// The file is compiled with -ffp-contract=off: every operation rounds as
+// written, and fused multiply-adds appear only where fma() is spelled out.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace w2d {
+
+// Stencil classes: 5-point (axis neighbours only), 9-point (axis and
+// diagonal) and 13-point (axis, diagonal and the axis neighbours two lines
+// away).  The isotropic comparison scheme is a 9-point class with other
+// weights.
+enum Kind : int { KIND5 = 0, KIND9 = 1, KIND13 = 2 };
+
+template <int K>
+struct KT {
+    static constexpr int R = (K == KIND13) ? 2 : 1;  // stencil radius
+    static constexpr bool DIAG = (K != KIND5);
+    static constexpr bool AX2 = (K == KIND13);
+};
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Values of one node's stencil neighbourhood: centre, axis neighbours
+// (E = i+1, W = i-1, N = j+1, S = j-1), diagonals, and axis neighbours two
+// lines away.  Unused members are ignored for smaller stencils.
+template <typename T>
+struct Nbh {
+    T C, E, W, N, S, NE, NW, SE, SW, EE, WW, NN, SS;
+};
+
+// sum_q w_q delta(q): each rotation sum of Sec. 6.2.1 (eq. notations2) is
+// evaluated as a sum of neighbour-minus-centre differences, pairing opposite
+// neighbours.  The differences keep the result accurate when the values are
+// close (the usual case for a smooth field), which matters in single
+// precision.
+template <int K, typename T>
+__device__ __forceinline__ T lap_diff(const Nbh<T>& v, T w10, T w11, T w20)
+{
+    const T C = v.C;
+    T s = w10 * (((v.E - C) + (v.W - C)) + ((v.N - C) + (v.S - C)));
+    if constexpr (KT<K>::DIAG) s = fmaT(w11, ((v.NE - C) + (v.SW - C)) + ((v.NW - C) + (v.SE - C)), s);
+    if constexpr (KT<K>::AX2) s = fmaT(w20, ((v.EE - C) + (v.WW - C)) + ((v.NN - C) + (v.SS - C)), s);
+    return s;
+}
+
+// The same operator as a weighted sum (wc = -4 (w10 + w11 + w20)).  Used
+// for the low-order part `lo` of the compensated state, whose own rounding
+// is far below the precision that is carried.
+template <int K>
+__device__ __forceinline__ float lap_sum(const Nbh<float>& v, float wc, float w10, float w11, float w20)
+{
+    float s = fmaT(w10, (v.E + v.W) + (v.N + v.S), wc * v.C);
+    if constexpr (KT<K>::DIAG) s = fmaT(w11, (v.NE + v.NW) + (v.SE + v.SW), s);
+    if constexpr (KT<K>::AX2) s = fmaT(w20, (v.EE + v.WW) + (v.NN + v.SS), s);
+    return s;
+}
+
+// FP64 two-step update (Sec. 3, eq. A2): u^{k+1} = 2u^k - u^{k-1} + s.
+__device__ __forceinline__ double f64_update(double C, double P, double s) { return ((C + C) - P) + s; }
+
+// Compensated FP32 two-step update.  The level is u + lo, d = u^k - u^{k-1}.
+// With s the stencil increment of u + lo: d <- d + s; the new level
+// u + lo + d is formed as y = d + lo followed by an error-free sum u + y =
+// t + e (Knuth's branch-free TwoSum), so that t is the new u and e the new lo.
+__device__ __forceinline__ void f32c_update(float su, float slo, float u, float lo, float d, float& u2,
+                                            float& lo2, float& d2)
+{
+    const float s = su + slo;
+    const float dn = d + s;
+    const float y = dn + lo;
+    const float t = u + y;
+    const float z = t - u;
+    lo2 = (u - (t - z)) + (y - z);
+    u2 = t;
+    d2 = dn;
+}
+
+// FP64 first step (Sec. 3, eq. A1): u^1 = (u^0 + sum wa delta(u^0)) +
+// tau (v^0 + sum wb epsilon(v^0)); sb = 0 for the conventional first step.
+__device__ __forceinline__ double first_update(double u0c, double sa, double v0c, double sb, double tau)
+{
+    return (u0c + sa) + tau * (v0c + sb);
+}
+
+// Split of an FP64 level into the compensated FP32 state.
+__device__ __forceinline__ void f32c_split(double cur, double prev, float& u, float& lo, float& d)
+{
+    u = (float)cur;
+    lo = (float)(cur - (double)u);
+    d = (float)(cur - prev);
+}
+
+__device__ __forceinline__ double f32c_join(float u, float lo) { return (double)u + (double)lo; }
+
+}  // namespace w2d

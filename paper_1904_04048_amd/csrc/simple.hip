@@ -1,0 +1,273 @@
+// One-node-per-thread kernels: the first step (run once per solve), state
+// conversions, copies, and a plain two-step sweep used for small grids and
+// as an in-library cross-check of the temporally blocked kernels.
+//
+// Every grid read goes through bc_load, which applies the boundary rule:
+// boundary nodes read as 0, a node one line outside reads as minus its
+// mirror image (only the 13-point stencil reaches there).
+#include "w2d.h"
+
+namespace w2d {
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+template <typename T>
+__device__ __forceinline__ T bc_load(const T* __restrict__ p, int nx, int ny, int ld, int i, int j)
+{
+    bool neg = false;
+    if (i < 0) { i = -i; neg = !neg; }
+    else if (i > nx - 1) { i = 2 * (nx - 1) - i; neg = !neg; }
+    if (j < 0) { j = -j; neg = !neg; }
+    else if (j > ny - 1) { j = 2 * (ny - 1) - j; neg = !neg; }
+    if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) return T(0);
+    const T v = p[(size_t)j * ld + i];
+    return neg ? -v : v;
+}
+
+template <int K, typename T>
+__device__ __forceinline__ Nbh<T> gather(const T* __restrict__ p, int nx, int ny, int ld, int i, int j)
+{
+    Nbh<T> v;
+    v.C = bc_load(p, nx, ny, ld, i, j);
+    v.E = bc_load(p, nx, ny, ld, i + 1, j);
+    v.W = bc_load(p, nx, ny, ld, i - 1, j);
+    v.N = bc_load(p, nx, ny, ld, i, j + 1);
+    v.S = bc_load(p, nx, ny, ld, i, j - 1);
+    if constexpr (KT<K>::DIAG) {
+        v.NE = bc_load(p, nx, ny, ld, i + 1, j + 1);
+        v.NW = bc_load(p, nx, ny, ld, i - 1, j + 1);
+        v.SE = bc_load(p, nx, ny, ld, i + 1, j - 1);
+        v.SW = bc_load(p, nx, ny, ld, i - 1, j - 1);
+    } else {
+        v.NE = v.NW = v.SE = v.SW = T(0);
+    }
+    if constexpr (KT<K>::AX2) {
+        v.EE = bc_load(p, nx, ny, ld, i + 2, j);
+        v.WW = bc_load(p, nx, ny, ld, i - 2, j);
+        v.NN = bc_load(p, nx, ny, ld, i, j + 2);
+        v.SS = bc_load(p, nx, ny, ld, i, j - 2);
+    } else {
+        v.EE = v.WW = v.NN = v.SS = T(0);
+    }
+    return v;
+}
+
+__device__ __forceinline__ bool interior(int nx, int ny, int i, int j)
+{
+    return i > 0 && i < nx - 1 && j > 0 && j < ny - 1;
+}
+
+template <int K>
+__global__ __launch_bounds__(BX* BY) void k_first_step(Grid g, FirstW w, const double* __restrict__ u0,
+                                                       const double* __restrict__ v0, double* __restrict__ u1)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    double r = 0.0;
+    if (interior(g.nx, g.ny, i, j)) {
+        const Nbh<double> a = gather<K>(u0, g.nx, g.ny, g.ld, i, j);
+        const Nbh<double> b = gather<K>(v0, g.nx, g.ny, g.ld, i, j);
+        const double sa = lap_diff<K>(a, w.a10, w.a11, w.a20);
+        const double sb = w.poisson ? lap_diff<K>(b, w.b10, w.b11, w.b20) : 0.0;
+        r = first_update(a.C, sa, b.C, sb, w.tau);
+    }
+    u1[(size_t)j * g.ld + i] = r;
+}
+
+template <int K>
+__global__ __launch_bounds__(BX* BY) void k_first_step_f32c(Grid g, FirstW w, const double* __restrict__ u0,
+                                                            const double* __restrict__ v0, float* __restrict__ u,
+                                                            float* __restrict__ lo, float* __restrict__ d)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    float ru = 0.f, rl = 0.f, rd = 0.f;
+    if (interior(g.nx, g.ny, i, j)) {
+        const Nbh<double> a = gather<K>(u0, g.nx, g.ny, g.ld, i, j);
+        const Nbh<double> b = gather<K>(v0, g.nx, g.ny, g.ld, i, j);
+        const double sa = lap_diff<K>(a, w.a10, w.a11, w.a20);
+        const double sb = w.poisson ? lap_diff<K>(b, w.b10, w.b11, w.b20) : 0.0;
+        f32c_split(first_update(a.C, sa, b.C, sb, w.tau), a.C, ru, rl, rd);
+    }
+    const size_t o = (size_t)j * g.ld + i;
+    u[o] = ru;
+    lo[o] = rl;
+    d[o] = rd;
+}
+
+template <int K>
+__global__ __launch_bounds__(BX* BY) void k_step_f64(Grid g, StepW64 w, const double* u_prev,
+                                                     const double* __restrict__ u_cur, double* u_next)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    double r = 0.0;
+    if (interior(g.nx, g.ny, i, j)) {
+        const Nbh<double> v = gather<K>(u_cur, g.nx, g.ny, g.ld, i, j);
+        r = f64_update(v.C, u_prev[(size_t)j * g.ld + i], lap_diff<K>(v, w.w10, w.w11, w.w20));
+    }
+    u_next[(size_t)j * g.ld + i] = r;
+}
+
+template <int K>
+__global__ __launch_bounds__(BX* BY) void k_step_f32c(Grid g, StepW32 w, const float* __restrict__ u,
+                                                      const float* __restrict__ lo, const float* __restrict__ d,
+                                                      float* __restrict__ u2, float* __restrict__ lo2,
+                                                      float* __restrict__ d2)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    float ru = 0.f, rl = 0.f, rd = 0.f;
+    const size_t o = (size_t)j * g.ld + i;
+    if (interior(g.nx, g.ny, i, j)) {
+        const Nbh<float> a = gather<K>(u, g.nx, g.ny, g.ld, i, j);
+        const Nbh<float> b = gather<K>(lo, g.nx, g.ny, g.ld, i, j);
+        const float su = lap_diff<K>(a, w.w10, w.w11, w.w20);
+        const float sl = lap_sum<K>(b, w.wc, w.w10, w.w11, w.w20);
+        f32c_update(su, sl, a.C, b.C, d[o], ru, rl, rd);
+    }
+    u2[o] = ru;
+    lo2[o] = rl;
+    d2[o] = rd;
+}
+
+__global__ __launch_bounds__(BX* BY) void k_init(Grid g, const double* __restrict__ p, const double* __restrict__ c,
+                                                 float* __restrict__ u, float* __restrict__ lo,
+                                                 float* __restrict__ d)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t o = (size_t)j * g.ld + i;
+    float ru = 0.f, rl = 0.f, rd = 0.f;
+    if (interior(g.nx, g.ny, i, j)) f32c_split(c[o], p[o], ru, rl, rd);
+    u[o] = ru;
+    lo[o] = rl;
+    d[o] = rd;
+}
+
+__global__ __launch_bounds__(BX* BY) void k_export(Grid g, const float* __restrict__ u, const float* __restrict__ lo,
+                                                   double* __restrict__ out)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t o = (size_t)j * g.ld + i;
+    out[o] = interior(g.nx, g.ny, i, j) ? f32c_join(u[o], lo[o]) : 0.0;
+}
+
+__global__ __launch_bounds__(BX* BY) void k_copy3(Grid g, const float* a, const float* b, const float* c, float* a2,
+                                                  float* b2, float* c2)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t o = (size_t)j * g.ld + i;
+    if (a) a2[o] = a[o];
+    if (b) b2[o] = b[o];
+    if (c) c2[o] = c[o];
+}
+
+__global__ __launch_bounds__(BX* BY) void k_copy2d(Grid g, const double* a, const double* b, double* a2, double* b2)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t o = (size_t)j * g.ld + i;
+    if (a) a2[o] = a[o];
+    if (b) b2[o] = b[o];
+}
+
+__global__ __launch_bounds__(BX* BY) void k_copy_interior(Grid g, const double* __restrict__ a,
+                                                          double* __restrict__ b)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t o = (size_t)j * g.ld + i;
+    b[o] = interior(g.nx, g.ny, i, j) ? a[o] : 0.0;
+}
+
+__global__ __launch_bounds__(BX* BY) void k_swap(Grid g, double* a, double* b)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t o = (size_t)j * g.ld + i;
+    const double t = a[o];
+    a[o] = b[o];
+    b[o] = t;
+}
+
+dim3 grid_of(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY); }
+const dim3 kBlock(BX, BY);
+
+}  // namespace
+
+#define W2D_DISPATCH_KIND(kind, KERNEL, ...)                                          \
+    switch (kind) {                                                                   \
+    case KIND5: KERNEL<KIND5><<<grid_of(g), kBlock, 0, s>>>(__VA_ARGS__); break;    \
+    case KIND9: KERNEL<KIND9><<<grid_of(g), kBlock, 0, s>>>(__VA_ARGS__); break;    \
+    case KIND13: KERNEL<KIND13><<<grid_of(g), kBlock, 0, s>>>(__VA_ARGS__); break;  \
+    default: return hipErrorInvalidValue;                                             \
+    }                                                                                 \
+    return hipGetLastError();
+
+hipError_t simple_first_step(const Grid& g, int kind, const FirstW& w, const double* u0, const double* v0,
+                             double* u1, hipStream_t s)
+{
+    W2D_DISPATCH_KIND(kind, k_first_step, g, w, u0, v0, u1)
+}
+
+hipError_t simple_first_step_f32c(const Grid& g, int kind, const FirstW& w, const double* u0, const double* v0,
+                                  float* u, float* lo, float* d, hipStream_t s)
+{
+    W2D_DISPATCH_KIND(kind, k_first_step_f32c, g, w, u0, v0, u, lo, d)
+}
+
+hipError_t simple_step_f64(const Grid& g, int kind, const StepW64& w, const double* u_prev, const double* u_cur,
+                           double* u_next, hipStream_t s)
+{
+    W2D_DISPATCH_KIND(kind, k_step_f64, g, w, u_prev, u_cur, u_next)
+}
+
+hipError_t simple_step_f32c(const Grid& g, int kind, const StepW32& w, const float* u, const float* lo,
+                            const float* d, float* u2, float* lo2, float* d2, hipStream_t s)
+{
+    W2D_DISPATCH_KIND(kind, k_step_f32c, g, w, u, lo, d, u2, lo2, d2)
+}
+
+hipError_t f32c_init(const Grid& g, const double* u_prev, const double* u_cur, float* u, float* lo, float* d,
+                     hipStream_t s)
+{
+    k_init<<<grid_of(g), kBlock, 0, s>>>(g, u_prev, u_cur, u, lo, d);
+    return hipGetLastError();
+}
+
+hipError_t f32c_export(const Grid& g, const float* u, const float* lo, double* out, hipStream_t s)
+{
+    k_export<<<grid_of(g), kBlock, 0, s>>>(g, u, lo, out);
+    return hipGetLastError();
+}
+
+hipError_t copy_f32x3(const Grid& g, const float* a, const float* b, const float* c, float* a2, float* b2,
+                      float* c2, hipStream_t s)
+{
+    k_copy3<<<grid_of(g), kBlock, 0, s>>>(g, a, b, c, a2, b2, c2);
+    return hipGetLastError();
+}
+
+hipError_t copy_f64x2(const Grid& g, const double* a, const double* b, double* a2, double* b2, hipStream_t s)
+{
+    k_copy2d<<<grid_of(g), kBlock, 0, s>>>(g, a, b, a2, b2);
+    return hipGetLastError();
+}
+
+hipError_t copy_interior_f64(const Grid& g, const double* a, double* b, hipStream_t s)
+{
+    k_copy_interior<<<grid_of(g), kBlock, 0, s>>>(g, a, b);
+    return hipGetLastError();
+}
+
+hipError_t swap_f64(const Grid& g, double* a, double* b, hipStream_t s)
+{
+    k_swap<<<grid_of(g), kBlock, 0, s>>>(g, a, b);
+    return hipGetLastError();
+}
+
+}  // namespace w2d

@@ -1,0 +1,74 @@
+// Internal declarations of the wave2d library (kernels and launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "point.h"
+
+namespace w2d {
+
+struct Grid {
+    int nx, ny, ld;
+};
+
+// Two-step weights (2 x the A-operator node weights).
+struct StepW64 {
+    double w10, w11, w20;
+};
+struct StepW32 {
+    float w10, w11, w20, wc;
+};
+// First-step weights: A node weights and B node weights divided by tau.
+struct FirstW {
+    double a10, a11, a20, b10, b11, b20, tau;
+    int poisson;  // 0: conventional first step (no v0 stencil term)
+};
+
+// ---- one-node-per-thread kernels (simple.hip) -----------------------------
+hipError_t simple_first_step(const Grid& g, int kind, const FirstW& w, const double* u0, const double* v0,
+                             double* u1, hipStream_t s);
+hipError_t simple_first_step_f32c(const Grid& g, int kind, const FirstW& w, const double* u0,
+                                  const double* v0, float* u, float* lo, float* d, hipStream_t s);
+// u_next may equal u_prev (in place).
+hipError_t simple_step_f64(const Grid& g, int kind, const StepW64& w, const double* u_prev,
+                           const double* u_cur, double* u_next, hipStream_t s);
+hipError_t simple_step_f32c(const Grid& g, int kind, const StepW32& w, const float* u, const float* lo,
+                            const float* d, float* u2, float* lo2, float* d2, hipStream_t s);
+hipError_t f32c_init(const Grid& g, const double* u_prev, const double* u_cur, float* u, float* lo, float* d,
+                     hipStream_t s);
+hipError_t f32c_export(const Grid& g, const float* u, const float* lo, double* out, hipStream_t s);
+// Element-wise copies of 1..3 grids (unused pointers NULL).
+hipError_t copy_f32x3(const Grid& g, const float* a, const float* b, const float* c, float* a2, float* b2,
+                      float* c2, hipStream_t s);
+hipError_t copy_f64x2(const Grid& g, const double* a, const double* b, double* a2, double* b2, hipStream_t s);
+hipError_t swap_f64(const Grid& g, double* a, double* b, hipStream_t s);
+// b <- a on interior nodes, 0 on the boundary.
+hipError_t copy_interior_f64(const Grid& g, const double* a, double* b, hipStream_t s);
+
+// ---- temporally blocked streaming kernels (stream.hip) ----------------------
+struct StreamShape {
+    int depth;  // time levels per pass
+    int rows;   // output rows per wavefront work item
+};
+// FP64: levels (p_in, c_in) = (k-1, k) -> (p_out, c_out) = (k+depth-1, k+depth).
+// With depth == 1 and p_out == p_in (in place), c_out must be NULL and only
+// level k+1 is written (into p_in).
+hipError_t stream_step_f64(const Grid& g, int kind, const StepW64& w, const StreamShape& sh,
+                           const double* p_in, const double* c_in, double* p_out, double* c_out,
+                           hipStream_t s);
+hipError_t stream_step_f32c(const Grid& g, int kind, const StepW32& w, const StreamShape& sh, const float* u,
+                            const float* lo, const float* d, float* u2, float* lo2, float* d2, hipStream_t s);
+bool stream_depth_supported(int depth);
+int stream_columns_per_wave(int precision);
+
+// ---- reductions (norms.hip) -------------------------------------------------
+// Partial sums into `part` (nblk x 4 doubles), then a single-block final
+// reduction into part[nblk*4 .. +4].
+int norms_blocks();
+hipError_t norms_f64(const Grid& g, const double* a, const double* b, double* part, hipStream_t s);
+hipError_t norms_f32c(const Grid& g, const float* u, const float* lo, const double* b, double* part,
+                      hipStream_t s);
+
+}  // namespace w2d

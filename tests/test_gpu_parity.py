@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: FP64 results within 1e-12 relative max-norm of the oracle (max|a-b| /
+max|b|); compensated FP32 results within 1e-5 relative max-norm; the
+temporally blocked kernels bit-identical to the one-node-per-thread kernels
+for every depth and segment length.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1904_04048_amd as w
+from tests.gpu_util import (dev_grid, empty_like_grid, padding_intact, rough_data, smooth_data)
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = [w.P5, w.P9, w.P13, w.C9]
+# (ny, nx, ld): minimum grids, ragged tails, several strips and segments, padded rows
+SHAPES = [(3, 3, 3), (4, 7, 9), (19, 5, 5), (67, 131, 131), (200, 129, 136), (131, 300, 300)]
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _lam(scheme, frac=0.9):
+    return frac * w.wave2d_lambda_max(scheme)
+
+
+def _flags_for(scheme, conv):
+    return w.FIRST_CONVENTIONAL if (conv or scheme == w.C9) else 0
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    yield
+    for p in (w.F64, w.F32C):
+        for s in SCHEMES:
+            w.wave2d_set_tuning(p, s)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}ld{s[2]}")
+@pytest.mark.parametrize("conv", [False, True])
+def test_first_step_fp64(scheme, shape, conv):
+    ny, nx, ld = shape
+    u0, v0 = rough_data(nx, ny, 1)
+    h = 1.0 / max(nx, ny)
+    tau = _lam(scheme) * h
+    fl = _flags_for(scheme, conv)
+    ref = oracle.first_step(u0, v0, h, tau, 1.0, scheme if scheme != w.C9 else oracle.C9, fl)
+    U0, V0 = dev_grid(u0, ld), dev_grid(v0, ld)
+    U1 = empty_like_grid(U0)
+    w.wave2d_first_step(U0, V0, U1, h, tau, 1.0, scheme, fl)
+    got = U1.cpu().numpy()
+    assert oracle.rel_max_err(got, ref) <= TOL64
+    assert padding_intact(U1)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}ld{s[2]}")
+@pytest.mark.parametrize("steps", [1, 2, 7, 40])
+def test_run_fp64_matches_oracle(scheme, shape, steps):
+    ny, nx, ld = shape
+    u0, v0 = rough_data(nx, ny, 2)
+    h = 1.0 / max(nx, ny)
+    tau = _lam(scheme) * h
+    fl = _flags_for(scheme, False)
+    orc_scheme = scheme if scheme != w.C9 else oracle.C9
+    rp, rc = oracle.run(u0, v0, h, tau, 1.0, orc_scheme, steps, fl)
+    U0, V0 = dev_grid(u0, ld), dev_grid(v0, ld)
+    UP, UC = empty_like_grid(U0), empty_like_grid(U0)
+    w.wave2d_run(U0, V0, UP, UC, h, tau, 1.0, scheme, steps, fl)
+    assert oracle.rel_max_err(UC.cpu().numpy(), rc) <= TOL64
+    assert oracle.rel_max_err(UP.cpu().numpy(), rp) <= TOL64
+    assert padding_intact(UP) and padding_intact(UC)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}ld{s[2]}")
+@pytest.mark.parametrize("steps", [1, 2, 9, 60])
+def test_run_f32c_matches_oracle(scheme, shape, steps):
+    ny, nx, ld = shape
+    (u0, v0), _ = smooth_data(nx, ny, 3)
+    h = 1.0 / max(nx, ny)
+    tau = _lam(scheme) * h
+    fl = _flags_for(scheme, False)
+    orc_scheme = scheme if scheme != w.C9 else oracle.C9
+    _, rc = oracle.run(u0, v0, h, tau, 1.0, orc_scheme, steps, fl)
+    U0, V0 = dev_grid(u0, ld), dev_grid(v0, ld)
+    u = empty_like_grid(U0, torch.float32)
+    lo, d = empty_like_grid(U0, torch.float32), empty_like_grid(U0, torch.float32)
+    w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, scheme, steps, fl)
+    out = empty_like_grid(U0)
+    w.wave2d_f32c_export(u, lo, out)
+    err = oracle.rel_max_err(out.cpu().numpy(), rc)
+    assert err <= TOL32, err
+    assert padding_intact(u) and padding_intact(lo) and padding_intact(d) and padding_intact(out)
+
+
+DEPTHS = [1, 2, 3, 4, 6]
+
+
+@pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
+@pytest.mark.parametrize("depth", DEPTHS)
+@pytest.mark.parametrize("rows", [8, 13, 64])
+def test_stream_fp64_bitwise_equals_simple(scheme, depth, rows):
+    ny, nx = 157, 263
+    u0, v0 = rough_data(nx, ny, 4)
+    h = 1.0 / 256
+    tau = _lam(scheme) * h
+    U0, V0 = dev_grid(u0), dev_grid(v0)
+    outs = []
+    for simple in (True, False):
+        if not simple:
+            w.wave2d_set_tuning(w.F64, scheme, depth, rows)
+        UP, UC = torch.empty_like(U0), torch.empty_like(U0)
+        w.wave2d_run(U0, V0, UP, UC, h, tau, 1.0, scheme, 23, w.KERNEL_SIMPLE if simple else 0)
+        outs.append((UP.clone(), UC.clone()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
+@pytest.mark.parametrize("depth", DEPTHS)
+@pytest.mark.parametrize("rows", [8, 13, 64])
+def test_stream_f32c_bitwise_equals_simple(scheme, depth, rows):
+    ny, nx = 157, 263
+    (u0, v0), _ = smooth_data(nx, ny, 5)
+    h = 1.0 / 256
+    tau = _lam(scheme) * h
+    U0, V0 = dev_grid(u0), dev_grid(v0)
+    outs = []
+    for simple in (True, False):
+        if not simple:
+            w.wave2d_set_tuning(w.F32C, scheme, depth, rows)
+        u = torch.empty(U0.shape, dtype=torch.float32, device=U0.device)
+        lo, d = torch.empty_like(u), torch.empty_like(u)
+        w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, scheme, 23, w.KERNEL_SIMPLE if simple else 0)
+        outs.append((u.clone(), lo.clone(), d.clone()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+
+
+def test_step_is_resumable_and_bitwise():
+    """run(K) equals run(K1) followed by step(K - K1), bit for bit; and a
+    second identical run gives identical bits (deterministic)."""
+    ny, nx = 90, 170
+    u0, v0 = rough_data(nx, ny, 6)
+    h = 1.0 / 169
+    tau = _lam(w.P9) * h
+    U0, V0 = dev_grid(u0), dev_grid(v0)
+    A_p, A_c = torch.empty_like(U0), torch.empty_like(U0)
+    w.wave2d_run(U0, V0, A_p, A_c, h, tau, 1.0, w.P9, 31)
+    B_p, B_c = torch.empty_like(U0), torch.empty_like(U0)
+    w.wave2d_run(U0, V0, B_p, B_c, h, tau, 1.0, w.P9, 12)
+    w.wave2d_step(B_p, B_c, h, tau, 1.0, w.P9, 19)
+    assert torch.equal(A_p, B_p) and torch.equal(A_c, B_c)
+    C_p, C_c = torch.empty_like(U0), torch.empty_like(U0)
+    w.wave2d_run(U0, V0, C_p, C_c, h, tau, 1.0, w.P9, 31)
+    assert torch.equal(A_c, C_c)
+    # compensated state likewise
+    u = torch.empty(U0.shape, dtype=torch.float32, device=U0.device)
+    lo, d = torch.empty_like(u), torch.empty_like(u)
+    w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, w.P9, 31)
+    u2, lo2, d2 = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
+    w.wave2d_f32c_run(U0, V0, u2, lo2, d2, h, tau, 1.0, w.P9, 10)
+    w.wave2d_f32c_step(u2, lo2, d2, h, tau, 1.0, w.P9, 21)
+    assert torch.equal(u, u2) and torch.equal(lo, lo2) and torch.equal(d, d2)
+
+
+def test_steps_zero_is_noop_and_explicit_workspace():
+    ny, nx = 40, 50
+    u0, v0 = rough_data(nx, ny, 7)
+    h, tau = 0.02, 0.01
+    U0, V0 = dev_grid(u0), dev_grid(v0)
+    P, C = torch.empty_like(U0), torch.empty_like(U0)
+    w.wave2d_run(U0, V0, P, C, h, tau, 1.0, w.P13, 5)
+    P0, C0 = P.clone(), C.clone()
+    w.wave2d_step(P, C, h, tau, 1.0, w.P13, 0)
+    assert torch.equal(P, P0) and torch.equal(C, C0)
+    work = torch.empty(w.wave2d_work_bytes(w.F64, nx, ny), dtype=torch.uint8, device=U0.device)
+    P1, C1 = P.clone(), C.clone()
+    w.wave2d_step(P, C, h, tau, 1.0, w.P13, 9)
+    w.wave2d_step(P1, C1, h, tau, 1.0, w.P13, 9, work=work)
+    assert torch.equal(P, P1) and torch.equal(C, C1)
+
+
+def test_f32c_init_export_roundtrip():
+    ny, nx = 33, 45
+    a, b = rough_data(nx, ny, 8)
+    A, B = dev_grid(a), dev_grid(b)
+    u = torch.empty(A.shape, dtype=torch.float32, device=A.device)
+    lo, d = torch.empty_like(u), torch.empty_like(u)
+    w.wave2d_f32c_init(B, A, u, lo, d)
+    out = torch.empty_like(A)
+    w.wave2d_f32c_export(u, lo, out)
+    ref = a.copy()
+    ref[0, :] = ref[-1, :] = ref[:, 0] = ref[:, -1] = 0
+    got = out.cpu().numpy()
+    # u + lo carries ~48 bits of the FP64 value
+    assert np.max(np.abs(got - ref)) <= 2.0 ** -46 * np.max(np.abs(ref))
+    dd = (a - b).astype(np.float32)
+    dd[0, :] = dd[-1, :] = dd[:, 0] = dd[:, -1] = 0
+    assert np.array_equal(d.cpu().numpy(), dd)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 700), (1025, 513), (300, 257)])
+def test_norms(shape):
+    ny, nx = shape
+    a, b = rough_data(nx, ny, 9)
+    got = w.wave2d_norms(dev_grid(a), dev_grid(b))
+    ref = oracle.norms(a, b)
+    assert got[0] == ref[0] and got[1] == ref[1]
+    assert got[2] == pytest.approx(ref[2], rel=1e-13) and got[3] == pytest.approx(ref[3], rel=1e-13)
+    # f32c form
+    u = torch.from_numpy(a.astype(np.float32)).cuda()
+    lo = torch.from_numpy((a - a.astype(np.float32).astype(np.float64)).astype(np.float32)).cuda()
+    got = w.wave2d_f32c_norms(u, lo, dev_grid(b))
+    ab = a.astype(np.float32).astype(np.float64) + lo.cpu().numpy().astype(np.float64)
+    ref = oracle.norms(ab, b)
+    assert got[0] == ref[0] and got[1] == ref[1]
+    assert got[2] == pytest.approx(ref[2], rel=1e-13)
+
+
+def test_norms_propagate_nan():
+    a = np.zeros((20, 20))
+    b = np.ones((20, 20))
+    a[7, 3] = np.nan
+    got = w.wave2d_norms(dev_grid(a), dev_grid(b))
+    assert math.isnan(got[0]) and math.isnan(got[2])
+
+
+def test_stability_limit_is_accepted_and_beyond_rejected():
+    ny, nx = 20, 20
+    h = 0.05
+    U0 = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    P, C = torch.empty_like(U0), torch.empty_like(U0)
+    for s in SCHEMES:
+        lam = w.wave2d_lambda_max(s)
+        w.wave2d_run(U0, U0.clone(), P, C, h, lam * h, 1.0, s, 3, _flags_for(s, False))
+        with pytest.raises(w.Wave2dError):
+            w.wave2d_run(U0, U0.clone(), P, C, h, lam * 1.001 * h, 1.0, s, 3, _flags_for(s, False))
+        w.wave2d_run(U0, U0.clone(), P, C, h, lam * 1.001 * h, 1.0, s, 3,
+                     _flags_for(s, False) | w.ALLOW_UNSTABLE)

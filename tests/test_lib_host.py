@@ -1,0 +1,150 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and its host-only logic (weights, limits, validation) is right.
+No test here enqueues device work: every call that takes grids is made with
+arguments that validation rejects before anything reaches the GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import derive
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wave2d.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1904_04048_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1904_04048_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wave2d_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_compiles_as_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "wave2d.h"\nint main(void){return WAVE2D_OK;}\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)],
+                   check=True)
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = header_functions()
+    assert len(names) >= 15
+    from paper_1904_04048_amd import _lib
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.exported_names(), f"binding lacks {n}"
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (wave2d_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_lambda_max(L):
+    import math
+    assert L.wave2d_lambda_max(5) == pytest.approx(math.sqrt(2) / 2, abs=1e-15)
+    assert L.wave2d_lambda_max(9) == pytest.approx(0.7962252170, abs=1e-9)
+    assert L.wave2d_lambda_max(13) == pytest.approx(1 / math.sqrt(2), abs=1e-15)
+    assert L.wave2d_lambda_max(109) == pytest.approx(math.sqrt(3) / 2, abs=1e-15)
+    assert L.wave2d_lambda_max(7) < 0
+
+
+@pytest.mark.parametrize("scheme", [5, 9, 13])
+@pytest.mark.parametrize("lam", [0.1, 0.45, 0.7])
+def test_weights_equal_exact_derivation(L, scheme, lam):
+    """The library's node weights equal A phi_q and B phi_q of the Sec. 4-5
+    construction (exact rationals evaluated at lambda)."""
+    w2, wa, wb = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    assert L.wave2d_weights(scheme, 0, lam, w2, wa, wb) == 0
+    nw = derive.node_weights(derive.SCHEME_M[scheme])
+    for k, q in enumerate([(1, 0), (1, 1), (2, 0)]):
+        A, B = nw.get(q, ({}, {}))
+        assert wa[k] == pytest.approx(derive.evaluate(A, lam), abs=2e-16)
+        assert wb[k] == pytest.approx(derive.evaluate(B, lam), abs=2e-16)
+        assert w2[k] == pytest.approx(2 * derive.evaluate(A, lam), abs=4e-16)
+    # the centre weight is implied: A 1 = 1 means w_c = 1 - 4 sum(w)
+    Ac = derive.evaluate(nw[(0, 0)][0], lam)
+    assert 1 - 4 * sum(wa) == pytest.approx(Ac, abs=1e-15)
+
+
+def test_conventional_and_isotropic_weights(L):
+    w2, wa, wb = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    assert L.wave2d_weights(9, 1, 0.5, w2, wa, wb) == 0
+    assert list(wb) == [0.0, 0.0, 0.0]
+    assert L.wave2d_weights(109, 0, 0.5, w2, wa, wb) == 0
+    # eq. comp9.2b: lambda^2 (2/3 delta(1,0) + 1/6 delta(1,1))
+    assert list(w2) == pytest.approx([0.25 * 2 / 3, 0.25 / 6, 0.0], abs=1e-16)
+    assert list(wb) == [0.0, 0.0, 0.0]
+    assert L.wave2d_weights(8, 0, 0.5, w2, wa, wb) == -1
+
+
+def test_status_strings(L):
+    assert L.wave2d_status_str(0) == b"WAVE2D_OK"
+    assert L.wave2d_status_str(-2) == b"WAVE2D_EUNSTABLE"
+    assert L.wave2d_status_str(-99) == b"WAVE2D_UNKNOWN"
+
+
+def test_work_bytes(L):
+    n = 1000 * 999
+    al = lambda v: (v + 255) // 256 * 256
+    assert L.wave2d_work_bytes(0, 1000, 999, 1000) == 2 * al(8 * n)
+    assert L.wave2d_work_bytes(1, 1000, 999, 1000) == 3 * al(4 * n)
+    assert L.wave2d_work_bytes(2, 10, 10, 10) == 0
+
+
+FAKE = ctypes.c_void_p(0x7f0000001000)   # never dereferenced: every call below fails validation
+FAKE2 = ctypes.c_void_p(0x7f0000801000)
+
+
+def _step(L, nx=10, ny=10, ld=10, h=0.1, tau=0.05, c=1.0, scheme=5, flags=0, steps=3, a=FAKE, b=FAKE2):
+    return L.wave2d_step(nx, ny, ld, h, tau, c, scheme, flags, steps, a, b, None, 0, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=2), -1), (dict(ny=1), -1), (dict(ld=9), -1), (dict(h=0.0), -1), (dict(tau=-1.0), -1),
+    (dict(c=float("nan")), -1), (dict(scheme=7), -1), (dict(flags=0x80), -1), (dict(steps=-1), -1),
+    (dict(a=ctypes.c_void_p(0)), -1), (dict(b=FAKE), -1),
+    (dict(tau=0.0708), -2), (dict(scheme=13, tau=0.0708), -2), (dict(scheme=9, tau=0.0797), -2),
+    (dict(nx=50000, ny=50000, ld=50000), -1),
+])
+def test_validation_rejects(L, kw, code):
+    assert _step(L, **kw) == code
+    assert L.wave2d_last_error() != b""
+
+
+def test_overlap_rejected_everywhere(L):
+    # u1 overlapping v0
+    assert L.wave2d_first_step(10, 10, 10, 0.1, 0.05, 1.0, 9, 0, FAKE, FAKE2,
+                               ctypes.c_void_p(0x7f0000801000 + 8 * 50), None) == -1
+    assert L.wave2d_f32c_step(10, 10, 10, 0.1, 0.05, 1.0, 9, 0, 1, FAKE, FAKE, FAKE2, None, 0, None) == -1
+    assert L.wave2d_run(10, 10, 10, 0.1, 0.05, 1.0, 9, 0, 2, FAKE, FAKE2, FAKE, FAKE2, None, 0, None) == -1
+    assert b"overlap" in L.wave2d_last_error()
+
+
+def test_explicit_workspace_too_small(L):
+    assert L.wave2d_f32c_step(10, 10, 10, 0.1, 0.05, 1.0, 9, 0, 5, FAKE, ctypes.c_void_p(0x7f0000001000 + 4096),
+                              FAKE2, ctypes.c_void_p(0x7f0001001000), 16, None) == -1
+    assert b"workspace" in L.wave2d_last_error()
+
+
+def test_tuning_roundtrip(L):
+    from paper_1904_04048_amd import _lib
+    t = _lib.Tuning(3, 40)
+    assert L.wave2d_set_tuning(1, 9, ctypes.byref(t)) == 0
+    o = _lib.Tuning()
+    assert L.wave2d_get_tuning(1, 9, 100, 100, ctypes.byref(o)) == 0
+    assert (o.depth, o.rows) == (3, 40)
+    assert L.wave2d_set_tuning(1, 9, None) == 0
+    bad = _lib.Tuning(5, 40)
+    assert L.wave2d_set_tuning(1, 9, ctypes.byref(bad)) == -1
+    bad = _lib.Tuning(2, 4)
+    assert L.wave2d_set_tuning(1, 9, ctypes.byref(bad)) == -1
