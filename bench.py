@@ -1,0 +1,278 @@
+"""Benchmark of the wave2d hot path on one MI355X.
+
+One step = one whole solve of the 9-point workload on a 4097 x 4097 grid
+(h = 1/4096, c = 1, lambda = 0.9 x the stability limit, 2000 time levels,
+u0 = sin 2 pi x sin 3 pi y, v0 = sin pi x sin pi y): the FP64 first step
+fused with the compensated-FP32 state split, 1999 temporally blocked
+two-step updates, and the FP64 error norms of the result against an FP64
+GPU solve of the same problem.  Inputs are resident on the GPU before the
+timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py --mode profile     # short run for rocprofv3 counter passes
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/s (GLUP/s) + % HBM roofline; served p50/p99 latency at fixed error"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+STATE_BYTES_PER_NODE = 24  # compensated state (u, lo, d): 12 B read + 12 B written per node per pass
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", choices=["bench", "profile", "summarize"], default="bench")
+    ap.add_argument("--prof-dir", default=os.path.join(ROOT, "gpurun_out"),
+                    help="summarize: directory holding the rocprofv3 csv output")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--kernel-launches", type=int, default=100)
+    return ap.parse_args()
+
+
+def exact_c2(p, k):
+    """Exact solution of the PDE for the 9-point workload's data at t = k tau."""
+    import numpy as np
+    t = k * p.tau
+    x = np.arange(p.nx) * p.h
+    y = np.arange(p.ny) * p.h
+    a = math.cos(math.sqrt(13.0) * math.pi * t)
+    b = math.sin(math.sqrt(2.0) * math.pi * t) / (math.sqrt(2.0) * math.pi)
+    return a * np.outer(np.sin(3 * math.pi * y), np.sin(2 * math.pi * x)) + \
+        b * np.outer(np.sin(math.pi * y), np.sin(math.pi * x))
+
+
+def cpu_baseline(p, u0, v0, budget_s=20.0):
+    """The FP64 CPU oracle on a bounded sample of the same solve: the first
+    step and as many two-step updates as fit in about budget_s seconds."""
+    import oracle
+    threads = oracle.get_threads()
+    t0 = time.perf_counter()
+    um1, u = u0.copy(), oracle.first_step(u0, v0, p.h, p.tau, p.c, p.scheme)
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    um1, u = oracle.steps(um1, u, p.h, p.tau, p.c, p.scheme, 2)
+    per = (time.perf_counter() - t0) / 2
+    n = int(max(4, min(2000, (budget_s - t_first) / max(per, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.steps(um1, u, p.h, p.tau, p.c, p.scheme, n)
+    dt = time.perf_counter() - t0
+    return {"value": round(p.interior * n / dt / 1e9, 5), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} two-step updates of the {p.nx}x{p.ny} 9-point FP64 solve ({dt:.1f} s timed)"}
+
+
+COUNTERS_MD = os.path.join(ROOT, "profiles", "k_stream_f32c_9pt_4097_counters.md")
+STATS_MD = os.path.join(ROOT, "profiles", "k_stream_f32c_9pt_4097_kernel_stats.md")
+
+
+def kernel_source_hash():
+    """Hash of the sources the step kernels are built from: a counter record
+    taken on other sources no longer describes the kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("stream.hip", "point.h", "w2d.h"):
+        h.update(open(os.path.join(ROOT, "paper_1904_04048_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_cfg):
+    """Measured HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on this kernel configuration."""
+    try:
+        text = open(COUNTERS_MD).read()
+        rec = json.loads(text.split("```json")[1].split("```")[0])
+    except (OSError, ValueError, IndexError):
+        return None
+    if rec.get("kernel_cfg") != kernel_cfg:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def summarize(prof_dir):
+    """Write the profiles/ summaries from rocprofv3 csv output: kernel-trace
+    statistics of a bench run, and FETCH_SIZE / WRITE_SIZE of the dominant
+    kernel scaled by what the same counters read for a plain copy."""
+    import csv
+    import statistics
+    stats = list(csv.DictReader(open(os.path.join(prof_dir, "prof_bench", "bench_kernel_stats.csv"))))
+    lines = ["# Kernel statistics: 9-point compensated-FP32 workload, 4097 x 4097, 2000 levels", "",
+             "Command (from the repository root, on one MI355X):", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o bench \\",
+             "        -- python3 bench.py --steps 2 --warmup 1 --no-cpu", "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in stats[:8]:
+        name = r["Name"].replace("w2d::(anonymous namespace)::", "").replace("|", "/")
+        if len(name) > 90:
+            name = name[:90] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | {float(r['MinNs'])/1e3:.1f} | "
+                     f"{float(r['MaxNs'])/1e3:.1f} | {float(r['Percentage']):.1f} |")
+    open(STATS_MD, "w").write("\n".join(lines) + "\n")
+
+    def per_kernel(path):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+    fetch = per_kernel(os.path.join(prof_dir, "pmc_fetch", "fetch_counter_collection.csv"))
+    write = per_kernel(os.path.join(prof_dir, "pmc_write", "write_counter_collection.csv"))
+    copy_bytes = 256 * 1024 * 1024  # bench.py --mode profile copies 256 MiB per dispatch
+    cf = [v for k, v in fetch.items() if "copyBuffer" in k][0]
+    cw = [v for k, v in write.items() if "copyBuffer" in k][0]
+    f_scale = copy_bytes / (statistics.median(cf) * 1024)
+    w_scale = copy_bytes / (statistics.median(cw) * 1024)
+    kf = [v for k, v in fetch.items() if "k_stream" in k][0]
+    kw = [v for k, v in write.items() if "k_stream" in k][0]
+    rd = statistics.median(kf) * 1024 * f_scale
+    wr = statistics.median(kw) * 1024 * w_scale
+    import torch  # noqa: F401  (tuning query loads the library)
+    import paper_1904_04048_amd as w
+    from paper_1904_04048_amd import workloads as W
+    p = W.c2()
+    depth, rows = w.wave2d_get_tuning(w.F32C, p.scheme, p.nx, p.ny)
+    cfg = {"kernel": "k_stream<PF32C,KIND9>", "depth": depth, "rows": rows, "grid": [p.nx, p.ny],
+           "source": kernel_source_hash()}
+    alg = STATE_BYTES_PER_NODE * p.nx * p.ny
+    rec = {"kernel_cfg": cfg, "hbm_bytes_per_launch": int(rd + wr), "read_bytes_per_launch": int(rd),
+           "write_bytes_per_launch": int(wr), "algorithmic_bytes_per_launch": alg,
+           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)}
+    md = ["# HBM traffic of the dominant kernel (compensated FP32, 9-point, 4097 x 4097)", "",
+          "Commands (from the repository root, one MI355X, one counter per run):", "",
+          "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --mode profile",
+          "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --mode profile",
+          "    python3 bench.py --mode summarize", "",
+          f"Copy calibration (256 MiB device copy): FETCH_SIZE reads {statistics.median(cf):.0f} KiB "
+          f"(scale {f_scale:.3f}), WRITE_SIZE reads {statistics.median(cw):.0f} KiB (scale {w_scale:.3f}).", "",
+          f"Step kernel, depth {depth}, rows {rows}: FETCH_SIZE {statistics.median(kf):.0f} KiB, "
+          f"WRITE_SIZE {statistics.median(kw):.0f} KiB per dispatch; scaled: read {rd/1e6:.1f} MB, "
+          f"write {wr/1e6:.1f} MB per launch against {alg/1e6:.1f} MB algorithmic "
+          f"({(rd + wr)/alg:.2f}x).", "", "```json", json.dumps(rec, indent=1), "```", ""]
+    open(COUNTERS_MD, "w").write("\n".join(md))
+    print(json.dumps(rec))
+
+
+def main():
+    args = parse()
+    if args.mode == "summarize":
+        summarize(args.prof_dir)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(multi-GPU decomposition is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1904_04048_amd as w
+    from paper_1904_04048_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    p = W.c2()
+    u0, v0 = p.data()
+    U0 = torch.from_numpy(u0).to(dev)
+    V0 = torch.from_numpy(v0).to(dev)
+    shape = (p.ny, p.nx)
+    u = torch.empty(shape, dtype=torch.float32, device=dev)
+    lo, d = torch.empty_like(u), torch.empty_like(u)
+    work = torch.empty(w.wave2d_work_bytes(w.F32C, p.nx, p.ny), dtype=torch.uint8, device=dev)
+    work64 = torch.empty(w.wave2d_work_bytes(w.F64, p.nx, p.ny), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    depth, rows = w.wave2d_get_tuning(w.F32C, p.scheme, p.nx, p.ny)
+    kernel_cfg = {"kernel": "k_stream<PF32C,KIND9>", "depth": depth, "rows": rows, "grid": [p.nx, p.ny],
+                  "source": kernel_source_hash()}
+
+    if args.mode == "profile":
+        # Copy calibration for the memory counters, then the dominant kernel.
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        w.wave2d_f32c_run(U0, V0, u, lo, d, p.h, p.tau, p.c, p.scheme, 1, work=work)
+        w.wave2d_f32c_step(u, lo, d, p.h, p.tau, p.c, p.scheme, depth * 6, work=work)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "done", "kernel_cfg": kernel_cfg, "copy_bytes": 2 * a.numel() * 4}))
+        return
+
+    # FP64 reference solve on the GPU (also the plain FP64 path's throughput).
+    UP, UC = torch.empty_like(U0), torch.empty_like(U0)
+    w.wave2d_run(U0, V0, UP, UC, p.h, p.tau, p.c, p.scheme, p.steps, work=work64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w.wave2d_run(U0, V0, UP, UC, p.h, p.tau, p.c, p.scheme, p.steps, work=work64)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    ref = UC
+
+    def one_solve():
+        w.wave2d_f32c_run(U0, V0, u, lo, d, p.h, p.tau, p.c, p.scheme, p.steps, work=work)
+        return w.wave2d_f32c_norms(u, lo, ref)  # synchronous
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nr = one_solve()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = elapsed / args.steps * 1e3
+    glups = p.lup * args.steps / elapsed / 1e9
+    err_fp64 = nr[0] / nr[1]
+
+    U_ex = torch.from_numpy(exact_c2(p, p.steps)).to(dev)
+    ne = w.wave2d_f32c_norms(u, lo, U_ex)
+    err_exact = ne[0] / ne[1]
+
+    # Dominant kernel: average launch time of the temporally blocked step
+    # kernel, from events on the stream it is launched on.
+    L = max(2, args.kernel_launches - args.kernel_launches % 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w.wave2d_f32c_step(u, lo, d, p.h, p.tau, p.c, p.scheme, depth * 2, work=work)
+    e0.record(stream)
+    w.wave2d_f32c_step(u, lo, d, p.h, p.tau, p.c, p.scheme, depth * L, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_launch = e0.elapsed_time(e1) / 1e3 / L
+    nodes = p.nx * p.ny
+    alg_bytes = STATE_BYTES_PER_NODE * nodes
+    achieved_gbs = alg_bytes / t_launch / 1e9
+    kernel_glups = p.interior * depth / t_launch / 1e9
+    traffic = traffic_record(kernel_cfg)
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kernel_cfg["kernel"], "depth": depth, "rows": rows,
+                "launch_us": round(t_launch * 1e6, 2), "kernel_glups": round(kernel_glups, 1),
+                "bytes_per_launch": alg_bytes}
+
+    out = {
+        "metric": METRIC, "value": round(glups, 2), "unit": "GLUP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "9-point, 4097x4097, 2000 levels, compensated FP32 (FP64 first step and norms)",
+                   "scheme": p.scheme, "nx": p.nx, "ny": p.ny, "steps_per_solve": p.steps,
+                   "lambda": p.lam, "lup_per_solve": p.lup, "parallelism": "single GPU"},
+        "error": {"max_rel_vs_gpu_fp64": err_fp64, "max_rel_vs_exact_pde": err_exact},
+        "fp64_path": {"value": round(p.lup / t64 / 1e9, 2), "unit": "GLUP/s", "ms_per_solve": round(t64 * 1e3, 2),
+                      "depth": w.wave2d_get_tuning(w.F64, p.scheme, p.nx, p.ny)[0]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, u0, v0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -212,14 +212,16 @@ struct TuneEntry {
 };
 TuneEntry g_tune[2][4] = {};
 
+// Shapes measured fastest on MI355X for 4097 x 4097 grids (depth x rows
+// sweep of the streaming kernels); overridable per process.
 wave2d_tuning default_tuning(int precision, int scheme, int64_t, int64_t)
 {
     wave2d_tuning t;
-    t.rows = 64;
+    t.rows = 16;
     if (precision == WAVE2D_F32C)
-        t.depth = (scheme == WAVE2D_P13) ? 3 : 4;
-    else
         t.depth = (scheme == WAVE2D_P13) ? 2 : 4;
+    else
+        t.depth = (scheme == WAVE2D_P13) ? 2 : 6;
     return t;
 }
 
