@@ -218,10 +218,8 @@ wave2d_tuning default_tuning(int precision, int scheme, int64_t, int64_t)
 {
     wave2d_tuning t;
     t.rows = 16;
-    if (precision == WAVE2D_F32C)
-        t.depth = (scheme == WAVE2D_P13) ? 2 : 4;
-    else
-        t.depth = (scheme == WAVE2D_P13) ? 2 : 6;
+    t.depth = (scheme == WAVE2D_P13) ? 3 : 6;
+    if (precision == WAVE2D_F64 && (scheme == WAVE2D_P9 || scheme == WAVE2D_C9)) t.rows = 24;
     return t;
 }
 
@@ -242,6 +240,7 @@ struct DevBuf {
 std::mutex g_buf_mu;
 std::map<std::pair<int, hipStream_t>, DevBuf> g_work;  // per (device, stream)
 std::map<int, DevBuf> g_part;                          // norms partials per device
+std::map<std::pair<int, hipStream_t>, Fork> g_fork;    // side stream per (device, stream)
 std::map<int, double*> g_host;                         // pinned host results per device
 
 int get_device(int* dev)
@@ -277,6 +276,25 @@ int library_work(hipStream_t s, size_t need, void** out)
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Side stream and fork/join events for the boundary-strip kernels of calls
+// on stream s (default priority, created on first use).
+int side_of(hipStream_t s, const Fork** out)
+{
+    int dev, r;
+    if ((r = get_device(&dev))) return r;
+    std::lock_guard<std::mutex> lk(g_buf_mu);
+    auto it = g_fork.find({dev, s});
+    if (it == g_fork.end()) {
+        Fork f{};
+        W2D_HIP(hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking));
+        W2D_HIP(hipEventCreateWithFlags(&f.ev_fork, hipEventDisableTiming));
+        W2D_HIP(hipEventCreateWithFlags(&f.ev_join, hipEventDisableTiming));
+        it = g_fork.emplace(std::make_pair(dev, s), f).first;
+    }
+    *out = &it->second;
+    return WAVE2D_OK;
+}
 
 size_t work_bytes_of(int precision, const Grid& g)
 {
@@ -356,7 +374,12 @@ int run_steps_f64(const Params& p, uint32_t flags, int64_t steps, double* up, do
         // In place: level k+1 overwrites level k-1, then the roles swap.
         double* a = up;
         double* b = uc;
-        const StreamShape sh{1, tn.rows};
+        const Fork* fk = nullptr;
+        if (!simple) {
+            int r = side_of(s, &fk);
+            if (r) return r;
+        }
+        const StreamShape sh{1, tn.rows, fk};
         for (int64_t k = 0; k < steps; ++k) {
             if (simple) W2D_HIP(simple_step_f64(g, p.kind, w, a, b, a, s));
             else W2D_HIP(stream_step_f64(g, p.kind, w, sh, a, b, a, nullptr, s));
@@ -371,11 +394,13 @@ int run_steps_f64(const Params& p, uint32_t flags, int64_t steps, double* up, do
     const size_t stride = align256((size_t)g.ld * g.ny * sizeof(double));
     double* wp = (double*)base;
     double* wc = (double*)(base + stride);
+    const Fork* fk;
+    if ((r = side_of(s, &fk))) return r;
     bool needs_copy;
     const std::vector<int> passes = plan_passes(steps, tn.depth, &needs_copy);
     double *ip = up, *ic = uc, *op = wp, *oc = wc;
     for (int d : passes) {
-        const StreamShape sh{d, tn.rows};
+        const StreamShape sh{d, tn.rows, fk};
         W2D_HIP(stream_step_f64(g, p.kind, w, sh, ip, ic, op, oc, s));
         std::swap(ip, op);
         std::swap(ic, oc);
@@ -399,6 +424,8 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
     float* wl = (float*)(base + stride);
     float* wd = (float*)(base + 2 * stride);
     const bool simple = flags & WAVE2D_KERNEL_SIMPLE;
+    const Fork* fk = nullptr;
+    if (!simple && (r = side_of(s, &fk))) return r;
     const wave2d_tuning tn = tuning_for(WAVE2D_F32C, p.scheme, g.nx, g.ny);
     bool needs_copy = false;
     std::vector<int> passes;
@@ -407,7 +434,7 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
     float *iu = u, *il = lo, *id = d, *ou = wu, *ol = wl, *od = wd;
     for (int dd : passes) {
         if (simple) W2D_HIP(simple_step_f32c(g, p.kind, w, iu, il, id, ou, ol, od, s));
-        else W2D_HIP(stream_step_f32c(g, p.kind, w, StreamShape{dd, tn.rows}, iu, il, id, ou, ol, od, s));
+        else W2D_HIP(stream_step_f32c(g, p.kind, w, StreamShape{dd, tn.rows, fk}, iu, il, id, ou, ol, od, s));
         std::swap(iu, ou);
         std::swap(il, ol);
         std::swap(id, od);
@@ -674,6 +701,14 @@ int wave2d_release(void)
         }
     }
     g_part.clear();
+    for (auto& kv : g_fork) {
+        (void)hipSetDevice(kv.first.first);
+        (void)hipStreamSynchronize(kv.second.side);
+        (void)hipStreamDestroy(kv.second.side);
+        (void)hipEventDestroy(kv.second.ev_fork);
+        (void)hipEventDestroy(kv.second.ev_join);
+    }
+    g_fork.clear();
     for (auto& kv : g_host)
         if (kv.second) (void)hipHostFree(kv.second);
     g_host.clear();

@@ -78,24 +78,177 @@ struct SArgs {
 constexpr int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 constexpr int mod_c(int a, int b) { return ((a % b) + b) % b; }
 
+// Halo columns per strip side, rounded up to even so that every lane's
+// column pair starts at an even column (8- or 16-byte aligned vectors).
+template <int R, int DEPTH>
+constexpr int halo_cols() { return (R * DEPTH + 1) & ~1; }
+
+// Raw buffer resources give loads and stores a scalar row offset and a
+// per-lane column offset that never changes along the stream, so the
+// address arithmetic stays off the vector ALU.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int CW>
+struct Vec {
+    T v[CW];
+};
+
+template <typename T, int CW>
+__device__ __forceinline__ Vec<T, CW> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    static_assert(sizeof(T) * CW == 8 || sizeof(T) * CW == 16, "vector width");
+    if constexpr (sizeof(T) * CW == 8)
+        return __builtin_bit_cast(Vec<T, CW>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(Vec<T, CW>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+template <typename T, int CW>
+__device__ __forceinline__ void buf_store(const Vec<T, CW>& x, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff)
+{
+    if constexpr (sizeof(T) * CW == 8) {
+        using V = unsigned __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, 0);
+    } else {
+        using V = unsigned __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, x), r, voff, soff, 0);
+    }
+}
+
+// Stencil update of one row segment (CW columns per lane) of level t from
+// the level t-1 window rows (centre, north, south, and the second ring for
+// the 13-point stencil) and the level t-1 point field.
+template <class Prec, int K, int CW>
+__device__ __forceinline__ void row_update(
+    const typename Prec::T (&Wc)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Wn)[Prec::NW][CW + 2 * KT<K>::R],
+    const typename Prec::T (&Ws)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Wnn)[Prec::NW][CW + 2 * KT<K>::R],
+    const typename Prec::T (&Wss)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Pin)[CW],
+    const typename Prec::W& w, typename Prec::T (&nv)[Prec::NW][CW + 2 * KT<K>::R], typename Prec::T (&np)[CW])
+{
+    using T = typename Prec::T;
+    constexpr int R = KT<K>::R;
+    constexpr int NW = Prec::NW;
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        const int e = R + m;
+        Nbh<T> nb[NW];
+#pragma unroll
+        for (int f = 0; f < NW; ++f) {
+            nb[f].C = Wc[f][e];
+            nb[f].E = Wc[f][e + 1];
+            nb[f].W = Wc[f][e - 1];
+            nb[f].N = Wn[f][e];
+            nb[f].S = Ws[f][e];
+            if constexpr (KT<K>::DIAG) {
+                nb[f].NE = Wn[f][e + 1];
+                nb[f].NW = Wn[f][e - 1];
+                nb[f].SE = Ws[f][e + 1];
+                nb[f].SW = Ws[f][e - 1];
+            } else {
+                nb[f].NE = nb[f].NW = nb[f].SE = nb[f].SW = T(0);
+            }
+            if constexpr (KT<K>::AX2) {
+                nb[f].EE = Wc[f][e + 2];
+                nb[f].WW = Wc[f][e - 2];
+                nb[f].NN = Wnn[f][e];
+                nb[f].SS = Wss[f][e];
+            } else {
+                nb[f].EE = nb[f].WW = nb[f].NN = nb[f].SS = T(0);
+            }
+        }
+        if constexpr (NW == 1) {
+            const T s = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
+            nv[0][e] = (T)f64_update((double)nb[0].C, (double)Pin[m], (double)s);
+            np[m] = nb[0].C;
+        } else {
+            const float su = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
+            const float sl = lap_sum<K>(nb[1], w.wc, w.w10, w.w11, w.w20);
+            float u2, l2, d2;
+            f32c_update(su, sl, nb[0].C, nb[1].C, Pin[m], u2, l2, d2);
+            nv[0][e] = u2;
+            nv[1][e] = l2;
+            np[m] = d2;
+        }
+    }
+}
+
+// Fill the R neighbour columns on each side of an extended row from the
+// adjacent lanes.
+template <typename T, int NW, int CW, int R>
+__device__ __forceinline__ void extend_row(T (&v)[NW][CW + 2 * R])
+{
+#pragma unroll
+    for (int f = 0; f < NW; ++f) {
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[f][e] = from_left(v[f][CW + e]);
+#pragma unroll
+        for (int e = R + CW; e < CW + 2 * R; ++e) v[f][e] = from_right(v[f][e - CW]);
+    }
+}
+
+// Work decomposition shared by the host and both kernels: strips of SW
+// output columns, segments of `rows` output rows, and the rectangle of
+// (strip, segment) pairs whose whole stream stays inside the grid interior
+// (strips [s_lo, s_lo + ns), segments [g_lo, g_lo + ng)).
+struct Decomp {
+    int nstrips, nseg, s_lo, ns, g_lo, ng;
+};
+
+// Map a boundary work id (the complement of the interior rectangle) to
+// (strip, segment): first every strip of the segments outside the interior
+// range, then the edge strips of the interior segments.
+__device__ __forceinline__ void boundary_item(const Decomp& d, int wid, int& strip, int& seg)
+{
+    const int outer = (d.nseg - d.ng) * d.nstrips;
+    if (wid < outer) {
+        const int k = wid / d.nstrips;
+        strip = wid % d.nstrips;
+        seg = (k < d.g_lo) ? k : k + d.ng;
+    } else {
+        const int w2 = wid - outer;
+        const int ne = d.nstrips - d.ns;
+        seg = d.g_lo + w2 / ne;
+        const int k = w2 % ne;
+        strip = (k < d.s_lo) ? k : k + d.ns;
+    }
+}
+
+// Renumber blocks so that each XCD (blocks are dealt round-robin to the 8
+// XCDs) gets a contiguous run of work items: neighbouring strips and
+// segments, whose halos overlap, then share one L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nblk = gridDim.x;
+    const int xcd = blockIdx.x % 8, kb = blockIdx.x / 8;
+    const int q8 = nblk / 8, r8 = nblk % 8;
+    return xcd * q8 + min(xcd, r8) + kb;
+}
+
+// General kernel: any work item, boundary rule applied everywhere.
 template <class Prec, int K, int DEPTH, int CW>
-__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typename Prec::T> a,
-                                                                      typename Prec::W w)
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_general(SArgs<typename Prec::T> a, Decomp dc,
+                                                                              int nwork, typename Prec::W w)
 {
     using T = typename Prec::T;
     constexpr int R = KT<K>::R;
     constexpr int NS = 2 * R + 1;  // rows in a level's window
     constexpr int NW = Prec::NW;
-    constexpr int H = R * DEPTH;   // halo columns on each side
-    constexpr int SW = kWave * CW - 2 * H;
+    constexpr int H = R * DEPTH;   // rows / columns a pass reaches beyond its outputs
+    constexpr int HP = halo_cols<R, DEPTH>();
+    constexpr int SW = kWave * CW - 2 * HP;
     constexpr int E = CW + 2 * R;  // extended row: R neighbours each side
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (wid >= a.nwork) return;  // whole wavefronts only
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wid >= nwork) return;  // whole wavefronts only
+    int strip, seg;
+    boundary_item(dc, wid, strip, seg);
     const int nx = a.g.nx, ny = a.g.ny, ld = a.g.ld;
-    const int strip = wid % a.nstrips, seg = wid / a.nstrips;
-    const int x0 = strip * SW - H;
+    const int x0 = strip * SW - HP;
     const int xl = x0 + lane * CW;
     const int y0 = seg * a.rows;
     const int y1 = min(y0 + a.rows, ny);
@@ -107,7 +260,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
     for (int m = 0; m < CW; ++m) {
         const int x = xl + m;
         ld_ok[m] = (x >= 0 && x < nx);
-        st_ok[m] = (x >= x0 + H && x < x0 + H + SW && x < nx);
+        st_ok[m] = (x >= x0 + HP && x < x0 + HP + SW && x < nx);
         ghost[m] = (R == 2) && (x == -1 || x == nx);
         zero_col[m] = !(x >= 1 && x <= nx - 2) && !ghost[m];
         const int src = (x == -1) ? 1 : nx - 2;
@@ -159,16 +312,6 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
             }
         }
     };
-    // Fill the R neighbour columns on each side from the adjacent lanes.
-    auto extend = [&](T (&v)[NW][E]) {
-#pragma unroll
-        for (int f = 0; f < NW; ++f) {
-#pragma unroll
-            for (int e = 0; e < R; ++e) v[f][e] = from_left(v[f][CW + e]);
-#pragma unroll
-            for (int e = R + CW; e < E; ++e) v[f][e] = from_right(v[f][e - CW]);
-        }
-    };
     auto zero_row = [&](T (&v)[NW][E]) {
 #pragma unroll
         for (int f = 0; f < NW; ++f)
@@ -182,11 +325,10 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
             for (int e = 0; e < E; ++e) dst[f][e] = -src[f][e];
     };
 
-    const bool t1_narrow = (DEPTH == 1);  // only the output region's point field is needed
-    // Issue the loads of level-0 row jj (window fields) and of the point
-    // field at row jj - R into the given slots.
-    // Addresses are clamped into the grid so that every load is in bounds;
-    // values from outside the wanted range are then replaced by 0.
+    constexpr bool t1_narrow = (DEPTH == 1);  // only the output region's point field is needed
+    // Loads of level-0 row jj (window fields) and of the point field at row
+    // jj - R, per element; addresses are clamped into the grid so that every
+    // load is in bounds, and values outside the wanted range become 0.
     auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
         const bool row_ok = (jj >= 0 && jj < ny);
         const int jp = jj - R;
@@ -217,12 +359,12 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
 #pragma unroll
         for (int ph = 0; ph < NS; ++ph) {
             const int j = jb + ph;
-            // 1. Finish level-0 row j (its loads were issued one row ago).
+            // Finish level-0 row j (its loads were issued one row ago).
             {
                 T(&v)[NW][E] = win[0][ph];
                 if (j >= 1 && j <= ny - 2) {
                     fix_columns(v);
-                    extend(v);
+                    extend_row<T, NW, CW, R>(v);
                 } else {
                     zero_row(v);
                 }
@@ -231,70 +373,21 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
                     if (j == ny) neg_copy(v, win[0][mod_c(ph - 2, NS)]);
                 }
             }
-            // 2. Levels 1..DEPTH at rows j - t*R; the next row's loads go out
-            //    right after level 1, whose inputs they overwrite.
+            // Levels 1..DEPTH at rows j - t*R; the next row's loads go out
+            // right after level 1, whose inputs they overwrite.
 #pragma unroll
             for (int t = 1; t <= DEPTH; ++t) {
-                if (t == 2) {
-                    // Slot (ph+1) of level 0 held row j+1-NS = j-2R, last
-                    // needed by level 1 at this row.
-                    issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
-                }
+                if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
                 const int y = j - t * R;
                 if (y < y0 - (DEPTH - t) * R || y > y1 - 1 + (DEPTH - t) * R) continue;
                 const int sy = mod_c(ph - t * R, NS);
-                const T(&Wc)[NW][E] = win[t - 1][sy];
-                const T(&Wn)[NW][E] = win[t - 1][mod_c(ph - t * R + 1, NS)];
-                const T(&Ws)[NW][E] = win[t - 1][mod_c(ph - t * R - 1, NS)];
-                const T(&Wnn)[NW][E] = win[t - 1][mod_c(ph - t * R + 2, NS)];
-                const T(&Wss)[NW][E] = win[t - 1][mod_c(ph - t * R - 2, NS)];
-                const T(&Pin)[CW] = pf[t - 1][sy];
                 T nv[NW][E];
                 T np[CW];
-                const bool inside = (y >= 1 && y <= ny - 2);
-                if (inside) {
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) {
-                        const int e = R + m;
-                        Nbh<T> nb[NW];
-#pragma unroll
-                        for (int f = 0; f < NW; ++f) {
-                            nb[f].C = Wc[f][e];
-                            nb[f].E = Wc[f][e + 1];
-                            nb[f].W = Wc[f][e - 1];
-                            nb[f].N = Wn[f][e];
-                            nb[f].S = Ws[f][e];
-                            if constexpr (KT<K>::DIAG) {
-                                nb[f].NE = Wn[f][e + 1];
-                                nb[f].NW = Wn[f][e - 1];
-                                nb[f].SE = Ws[f][e + 1];
-                                nb[f].SW = Ws[f][e - 1];
-                            } else {
-                                nb[f].NE = nb[f].NW = nb[f].SE = nb[f].SW = T(0);
-                            }
-                            if constexpr (KT<K>::AX2) {
-                                nb[f].EE = Wc[f][e + 2];
-                                nb[f].WW = Wc[f][e - 2];
-                                nb[f].NN = Wnn[f][e];
-                                nb[f].SS = Wss[f][e];
-                            } else {
-                                nb[f].EE = nb[f].WW = nb[f].NN = nb[f].SS = T(0);
-                            }
-                        }
-                        if constexpr (NW == 1) {
-                            const T s = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
-                            nv[0][e] = (T)f64_update((double)nb[0].C, (double)Pin[m], (double)s);
-                            np[m] = nb[0].C;
-                        } else {
-                            const float su = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
-                            const float sl = lap_sum<K>(nb[1], w.wc, w.w10, w.w11, w.w20);
-                            float u2, l2, d2;
-                            f32c_update(su, sl, nb[0].C, nb[1].C, Pin[m], u2, l2, d2);
-                            nv[0][e] = u2;
-                            nv[1][e] = l2;
-                            np[m] = d2;
-                        }
-                    }
+                if (y >= 1 && y <= ny - 2) {
+                    row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                            win[t - 1][mod_c(ph - t * R - 1, NS)],
+                                            win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                            win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
                     fix_columns(nv);
                     if (edge) {
 #pragma unroll
@@ -310,7 +403,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
                     for (int m = 0; m < CW; ++m) np[m] = T(0);
                 }
                 if (t < DEPTH) {
-                    extend(nv);
+                    extend_row<T, NW, CW, R>(nv);
                     T(&dst)[NW][E] = win[t][sy];
 #pragma unroll
                     for (int f = 0; f < NW; ++f)
@@ -339,22 +432,217 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream(SArgs<typen
     }
 }
 
+// Interior kernel: work items whose strip lies in columns [1, nx-2] and
+// whose whole stream (rows y0 - H - NS .. y1 + H + 2 NS) lies in rows
+// [2, ny-3], so no boundary rule applies and every access is in bounds
+// without checks.  Loads and stores are one vector per field through
+// buffer resources with a scalar row offset.
+template <class Prec, int K, int DEPTH, int CW>
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SArgs<typename Prec::T> a, Decomp dc,
+                                                                               typename Prec::W w)
+{
+    using T = typename Prec::T;
+    constexpr int R = KT<K>::R;
+    constexpr int NS = 2 * R + 1;
+    constexpr int NW = Prec::NW;
+    constexpr int H = R * DEPTH;
+    constexpr int HP = halo_cols<R, DEPTH>();
+    constexpr int SW = kWave * CW - 2 * HP;
+    constexpr int E = CW + 2 * R;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    // Wave-uniform from here on: keeps the work item and the buffer
+    // resources in scalar registers.
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wid >= dc.ns * dc.ng) return;
+    const int strip = dc.s_lo + wid % dc.ns;
+    const int seg = dc.g_lo + wid / dc.ns;
+    const int ld = a.g.ld;
+    const int x0 = strip * SW - HP;
+    const int xl = x0 + lane * CW;
+    const int y0 = seg * a.rows;
+    const int y1 = min(y0 + a.rows, a.g.ny);
+    const bool st_lane = (xl >= x0 + HP) && (xl < x0 + HP + SW);
+
+    const int jA = floor_div(y0 - H, NS) * NS;
+    const int jhi = y1 - 1 + H;
+    // Rows this wave touches: loads from jA - R, stores up to y1 - 1, loads
+    // up to the last iteration's next row (< jhi + NS + 1).
+    const int base_row = jA - NS;
+    const uint32_t rbytes = (uint32_t)((jhi + 2 * NS + 1 - base_row) * ld * (int)sizeof(T));
+    __amdgpu_buffer_rsrc_t rs_in[2], rs_out[2];
+    rs_in[0] = make_rsrc(a.in_w0 + (size_t)base_row * ld, rbytes);
+    rs_in[1] = make_rsrc((NW > 1 ? a.in_w1 : a.in_w0) + (size_t)base_row * ld, rbytes);
+    rs_out[0] = make_rsrc(a.out_w0 + (size_t)base_row * ld, rbytes);
+    rs_out[1] = make_rsrc((NW > 1 ? a.out_w1 : a.out_w0) + (size_t)base_row * ld, rbytes);
+    const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.in_p + (size_t)base_row * ld, rbytes);
+    const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc((a.out_p ? a.out_p : a.out_w0) + (size_t)base_row * ld, rbytes);
+    const uint32_t voff = (uint32_t)(xl * (int)sizeof(T));
+    const int row_bytes = ld * (int)sizeof(T);
+
+    T win[DEPTH][NS][NW][E];
+    T pf[DEPTH][NS][CW];
+#pragma unroll
+    for (int t = 0; t < DEPTH; ++t)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int f = 0; f < NW; ++f)
+#pragma unroll
+                for (int e = 0; e < E; ++e) win[t][s][f][e] = T(0);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) pf[t][s][m] = T(0);
+        }
+
+    // With DEPTH 1 the point field is read only on this segment's rows and
+    // output columns (it may be the array being written in place).
+    auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
+        const uint32_t so = (uint32_t)((jj - base_row) * row_bytes);
+#pragma unroll
+        for (int f = 0; f < NW; ++f) {
+            const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) v[f][R + m] = x.v[m];
+        }
+        int jp = jj - R;
+        if constexpr (DEPTH == 1) {
+            jp = min(max(jp, y0), y1 - 1);
+            if (!st_lane) return;
+        }
+        const Vec<T, CW> x = buf_load<T, CW>(rs_pin, voff, (uint32_t)((jp - base_row) * row_bytes));
+#pragma unroll
+        for (int m = 0; m < CW; ++m) p[m] = x.v[m];
+    };
+
+    auto phase = [&](int ph, int j, bool warm) {
+        extend_row<T, NW, CW, R>(win[0][ph]);
+#pragma unroll
+        for (int t = 1; t <= DEPTH; ++t) {
+            if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
+            const int y = j - t * R;
+            if (warm && y < y0 - (DEPTH - t) * R) continue;
+            const int sy = mod_c(ph - t * R, NS);
+            T nv[NW][E];
+            T np[CW];
+            row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                    win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                    win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
+            if (t < DEPTH) {
+                extend_row<T, NW, CW, R>(nv);
+                T(&dst)[NW][E] = win[t][sy];
+#pragma unroll
+                for (int f = 0; f < NW; ++f)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) dst[f][e] = nv[f][e];
+#pragma unroll
+                for (int m = 0; m < CW; ++m) pf[t][sy][m] = np[m];
+            } else if (y >= y0 && y < y1 && st_lane) {
+                const uint32_t so = (uint32_t)((y - base_row) * row_bytes);
+#pragma unroll
+                for (int f = 0; f < NW; ++f) {
+                    Vec<T, CW> x;
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) x.v[m] = nv[f][R + m];
+                    buf_store<T, CW>(x, rs_out[f], voff, so);
+                }
+                if (a.out_p) {
+                    Vec<T, CW> x;
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) x.v[m] = np[m];
+                    buf_store<T, CW>(x, rs_pout, voff, so);
+                }
+            }
+        }
+        if constexpr (DEPTH == 1) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
+    };
+
+    issue_loads(jA, win[0][0], pf[0][mod_c(-R, NS)]);
+    int jb = jA;
+    // Warm-up: levels whose rows are not yet needed are skipped.
+    for (; jb <= jhi && jb < y0 + H; jb += NS) {
+#pragma unroll
+        for (int ph = 0; ph < NS; ++ph) phase(ph, jb + ph, true);
+    }
+    for (; jb <= jhi; jb += NS) {
+#pragma unroll
+        for (int ph = 0; ph < NS; ++ph) phase(ph, jb + ph, false);
+    }
+}
+
+template <int R, int DEPTH, int CW>
+Decomp make_decomp(const Grid& g, int rows)
+{
+    constexpr int NS = 2 * R + 1;
+    constexpr int H = R * DEPTH;
+    constexpr int HP = halo_cols<R, DEPTH>();
+    constexpr int SW = kWave * CW - 2 * HP;
+    Decomp d;
+    d.nstrips = (g.nx + SW - 1) / SW;
+    d.nseg = (g.ny + rows - 1) / rows;
+    d.s_lo = d.nstrips;
+    int s_hi = -1;
+    for (int s = 0; s < d.nstrips; ++s) {
+        const int x0 = s * SW - HP;
+        if (x0 >= 1 && x0 + kWave * CW - 1 <= g.nx - 2) {
+            d.s_lo = min(d.s_lo, s);
+            s_hi = max(s_hi, s);
+        }
+    }
+    d.ns = (s_hi >= d.s_lo) ? s_hi - d.s_lo + 1 : 0;
+    d.g_lo = d.nseg;
+    int g_hi = -1;
+    for (int k = 0; k < d.nseg; ++k) {
+        const int y0 = k * rows, y1 = min(y0 + rows, g.ny);
+        if (y0 - H - NS >= 2 && y1 + H + 2 * NS <= g.ny - 3) {
+            d.g_lo = min(d.g_lo, k);
+            g_hi = max(g_hi, k);
+        }
+    }
+    d.ng = (g_hi >= d.g_lo) ? g_hi - d.g_lo + 1 : 0;
+    if (d.ns == 0 || d.ng == 0) {
+        d.ns = d.ng = 0;
+        d.s_lo = d.g_lo = 0;
+    }
+    return d;
+}
+
 template <class Prec, int K, int DEPTH>
-hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, SArgs<typename Prec::T> a,
-                        hipStream_t s)
+hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, const Fork* fork,
+                        SArgs<typename Prec::T> a, hipStream_t s)
 {
     constexpr int CW = 2;
     constexpr int R = KT<K>::R;
-    constexpr int SW = kWave * CW - 2 * R * DEPTH;
+    constexpr int SW = kWave * CW - 2 * halo_cols<R, DEPTH>();
     static_assert(SW > 0, "strip too narrow");
     a.g = g;
     a.rows = rows;
-    a.nstrips = (g.nx + SW - 1) / SW;
-    const int nseg = (g.ny + rows - 1) / rows;
-    a.nwork = a.nstrips * nseg;
-    const int blocks = (a.nwork + kWavesPerBlock - 1) / kWavesPerBlock;
-    k_stream<Prec, K, DEPTH, CW><<<blocks, kWave * kWavesPerBlock, 0, s>>>(a, w);
-    return hipGetLastError();
+    const Decomp dc = make_decomp<R, DEPTH, CW>(g, rows);
+    a.nstrips = dc.nstrips;
+    a.nwork = dc.nstrips * dc.nseg;
+    const int nb = a.nwork - dc.ns * dc.ng;
+    const int ni = dc.ns * dc.ng;
+    // The two kernels write disjoint nodes and read only the input state, so
+    // the boundary kernel (few, long-lived waves) may run beside the interior one.
+    const bool split = fork && nb > 0 && ni > 0;
+    hipError_t e;
+    if (split) {
+        if ((e = hipEventRecord(fork->ev_fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(fork->side, fork->ev_fork, 0)) != hipSuccess) return e;
+    }
+    if (nb > 0) {
+        const int blocks = (nb + kWavesPerBlock - 1) / kWavesPerBlock;
+        k_stream_general<Prec, K, DEPTH, CW>
+            <<<blocks, kWave * kWavesPerBlock, 0, split ? fork->side : s>>>(a, dc, nb, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (split && (e = hipEventRecord(fork->ev_join, fork->side)) != hipSuccess) return e;
+    if (ni > 0) {
+        const int blocks = (ni + kWavesPerBlock - 1) / kWavesPerBlock;
+        k_stream_interior<Prec, K, DEPTH, CW><<<blocks, kWave * kWavesPerBlock, 0, s>>>(a, dc, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (split && (e = hipStreamWaitEvent(s, fork->ev_join, 0)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 template <class Prec, int K>
@@ -362,12 +650,12 @@ hipError_t launch_kind(const Grid& g, const typename Prec::W& w, const StreamSha
                        hipStream_t s)
 {
     switch (sh.depth) {
-    case 1: return launch_depth<Prec, K, 1>(g, w, sh.rows, a, s);
-    case 2: return launch_depth<Prec, K, 2>(g, w, sh.rows, a, s);
-    case 3: return launch_depth<Prec, K, 3>(g, w, sh.rows, a, s);
-    case 4: return launch_depth<Prec, K, 4>(g, w, sh.rows, a, s);
-    case 6: return launch_depth<Prec, K, 6>(g, w, sh.rows, a, s);
-    case 8: return launch_depth<Prec, K, 8>(g, w, sh.rows, a, s);
+    case 1: return launch_depth<Prec, K, 1>(g, w, sh.rows, sh.fork, a, s);
+    case 2: return launch_depth<Prec, K, 2>(g, w, sh.rows, sh.fork, a, s);
+    case 3: return launch_depth<Prec, K, 3>(g, w, sh.rows, sh.fork, a, s);
+    case 4: return launch_depth<Prec, K, 4>(g, w, sh.rows, sh.fork, a, s);
+    case 6: return launch_depth<Prec, K, 6>(g, w, sh.rows, sh.fork, a, s);
+    case 8: return launch_depth<Prec, K, 8>(g, w, sh.rows, sh.fork, a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -48,9 +48,16 @@ hipError_t swap_f64(const Grid& g, double* a, double* b, hipStream_t s);
 hipError_t copy_interior_f64(const Grid& g, const double* a, double* b, hipStream_t s);
 
 // ---- temporally blocked streaming kernels (stream.hip) ----------------------
+// Optional side stream: the boundary-strip kernel of a pass runs there,
+// concurrently with the interior kernel, fenced by two events.
+struct Fork {
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
+};
 struct StreamShape {
-    int depth;  // time levels per pass
-    int rows;   // output rows per wavefront work item
+    int depth;                 // time levels per pass
+    int rows;                  // output rows per wavefront work item
+    const Fork* fork = nullptr;
 };
 // FP64: levels (p_in, c_in) = (k-1, k) -> (p_out, c_out) = (k+depth-1, k+depth).
 // With depth == 1 and p_out == p_in (in place), c_out must be NULL and only
