@@ -16,15 +16,16 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (ALLOW_UNSTABLE, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13,
-                   Tuning, Wave2dError)
+from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13,
+                   BatchStats, Instance, Tuning, Wave2dError)
 
 __all__ = [
     "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE",
     "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_work_bytes", "wave2d_first_step",
     "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
-    "wave2d_release",
+    "wave2d_release", "wave2d_autotune", "wave2d_batch_create", "wave2d_batch_run", "wave2d_batch_stats_get",
+    "wave2d_batch_destroy", "BATCH_GRAPH",
 ]
 
 
@@ -164,3 +165,45 @@ def wave2d_get_tuning(precision: int, scheme: int, nx: int = 0, ny: int = 0):
 
 def wave2d_release():
     _lib.check(_lib.load().wave2d_release())
+
+
+def wave2d_autotune(precision: int, scheme: int, nx: int, ny: int):
+    """Time every register-resident launch shape on an nx x ny grid, select
+    the fastest for this process and return (depth, rows)."""
+    import torch
+    t = Tuning()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(_lib.load().wave2d_autotune(precision, scheme, nx, ny, s, ctypes.byref(t)))
+    return t.depth, t.rows
+
+
+def wave2d_batch_create(instances, flags: int = 0):
+    """instances: list of dicts with keys nx, ny, ld, h, tau, c, scheme, flags,
+    steps and tensors u0, v0 (float64) and u, lo, d (float32).  Returns an
+    opaque handle (keep the tensors alive while the batch exists)."""
+    arr = (Instance * len(instances))()
+    for k, it in enumerate(instances):
+        u0 = it["u0"]
+        ny, nx = u0.shape
+        arr[k] = Instance(nx, ny, u0.stride(0), it["h"], it["tau"], it.get("c", 1.0), it["scheme"],
+                          it.get("flags", 0), it["steps"], u0.data_ptr(), it["v0"].data_ptr(),
+                          it["u"].data_ptr(), it["lo"].data_ptr(), it["d"].data_ptr())
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().wave2d_batch_create(arr, len(instances), flags, ctypes.byref(h)))
+    return h
+
+
+def wave2d_batch_run(batch):
+    import torch
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(_lib.load().wave2d_batch_run(batch, s))
+
+
+def wave2d_batch_stats_get(batch):
+    st = BatchStats()
+    _lib.check(_lib.load().wave2d_batch_stats_get(batch, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in BatchStats._fields_}
+
+
+def wave2d_batch_destroy(batch):
+    _lib.check(_lib.load().wave2d_batch_destroy(batch))

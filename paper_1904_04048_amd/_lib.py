@@ -22,8 +22,24 @@ P = ctypes.c_void_p
 SZ = ctypes.c_size_t
 
 
+BATCH_GRAPH = 0x10000
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("rows", ctypes.c_int32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("h", ctypes.c_double), ("tau", ctypes.c_double), ("c", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("flags", ctypes.c_uint32), ("steps", ctypes.c_int64),
+                ("u0", ctypes.c_void_p), ("v0", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("lo", ctypes.c_void_p), ("d", ctypes.c_void_p)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_int64), ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("lup", ctypes.c_int64), ("state_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64)]
 
 
 _SIGS = {
@@ -44,6 +60,11 @@ _SIGS = {
     "wave2d_set_tuning": (I, [I, I, P]),
     "wave2d_get_tuning": (I, [I, I, I64, I64, P]),
     "wave2d_release": (I, []),
+    "wave2d_autotune": (I, [I, I, I64, I64, P, P]),
+    "wave2d_batch_create": (I, [P, I64, U32, P]),
+    "wave2d_batch_run": (I, [P, P]),
+    "wave2d_batch_stats_get": (I, [P, P]),
+    "wave2d_batch_destroy": (I, [P]),
 }
 
 _lib = None

@@ -13,12 +13,11 @@
 #include <utility>
 #include <vector>
 
-#include "w2d.h"
-#include "wave2d.h"
+#include "host.h"
 
 using namespace w2d;
 
-namespace {
+namespace w2d_host {
 
 thread_local std::string g_last_error;
 
@@ -41,11 +40,6 @@ int hip_fail(hipError_t e, const char* what)
     return fail(WAVE2D_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define W2D_HIP(call)                                   \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
 
 int kind_of(int scheme)
 {
@@ -117,14 +111,6 @@ double lambda_max_of(int scheme)
     }
 }
 
-struct Params {
-    Grid g;
-    int scheme;
-    int kind;
-    double lam;
-    double wa[3], wb[3];
-    bool has_b;
-};
 
 int check_finite_pos(double v, const char* name)
 {
@@ -221,6 +207,15 @@ wave2d_tuning default_tuning(int precision, int scheme, int64_t, int64_t)
     t.depth = (scheme == WAVE2D_P13) ? 3 : 6;
     if (precision == WAVE2D_F64 && (scheme == WAVE2D_P9 || scheme == WAVE2D_C9)) t.rows = 24;
     return t;
+}
+
+void set_tuning_entry(int precision, int scheme, const wave2d_tuning& t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int si = scheme_index(scheme);
+    if (si < 0) return;
+    g_tune[precision][si].set = true;
+    g_tune[precision][si].t = t;
 }
 
 wave2d_tuning tuning_for(int precision, int scheme, int64_t nx, int64_t ny)
@@ -490,7 +485,9 @@ int check_grid_only(int64_t nx, int64_t ny, int64_t ld, Grid* g)
     return WAVE2D_OK;
 }
 
-}  // namespace
+}  // namespace w2d_host
+
+using namespace w2d_host;
 
 // ======================= exported entry points =================================
 

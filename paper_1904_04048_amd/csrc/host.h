@@ -1,0 +1,55 @@
+// Host-side helpers shared by the C-ABI translation units (validation,
+// weights, tuning, library-owned buffers, error reporting).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <initializer_list>
+#include <utility>
+#include <vector>
+
+#include "w2d.h"
+#include "wave2d.h"
+
+namespace w2d_host {
+
+using w2d::FirstW;
+using w2d::Fork;
+using w2d::Grid;
+using w2d::StepW32;
+using w2d::StepW64;
+
+struct Params {
+    Grid g;
+    int scheme;
+    int kind;
+    double lam;
+    double wa[3], wb[3];
+    bool has_b;
+};
+
+int fail(int status, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int kind_of(int scheme);
+int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c, int scheme, uint32_t flags,
+             Params* p);
+StepW64 step_w64(const Params& p);
+StepW32 step_w32(const Params& p);
+FirstW first_w(const Params& p, uint32_t flags, double tau);
+bool overlap(const void* a, size_t na, const void* b, size_t nb);
+size_t grid_bytes(const Grid& g, size_t elt);
+int check_ptrs(const Grid& g, std::initializer_list<std::pair<const void*, size_t>> arrs);
+wave2d_tuning tuning_for(int precision, int scheme, int64_t nx, int64_t ny);
+void set_tuning_entry(int precision, int scheme, const wave2d_tuning& t);
+int get_device(int* dev);
+size_t align256(size_t v);
+int side_of(hipStream_t s, const Fork** out);
+
+}  // namespace w2d_host
+
+#define W2D_HIP(call)                                                 \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return w2d_host::hip_fail(e_, #call);   \
+    } while (0)

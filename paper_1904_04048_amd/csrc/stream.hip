@@ -228,10 +228,11 @@ __device__ __forceinline__ int xcd_block()
     return xcd * q8 + min(xcd, r8) + kb;
 }
 
-// General kernel: any work item, boundary rule applied everywhere.
+// General body: any work item, boundary rule applied everywhere.  `wid`
+// is a wave-uniform boundary work id in [0, nwork).
 template <class Prec, int K, int DEPTH, int CW>
-__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_general(SArgs<typename Prec::T> a, Decomp dc,
-                                                                              int nwork, typename Prec::W w)
+__device__ __forceinline__ void general_body(const SArgs<typename Prec::T>& a, const Decomp& dc, int wid,
+                                             const typename Prec::W& w)
 {
     using T = typename Prec::T;
     constexpr int R = KT<K>::R;
@@ -243,8 +244,6 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_general(SAr
     constexpr int E = CW + 2 * R;  // extended row: R neighbours each side
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (threadIdx.x >> 6));
-    if (wid >= nwork) return;  // whole wavefronts only
     int strip, seg;
     boundary_item(dc, wid, strip, seg);
     const int nx = a.g.nx, ny = a.g.ny, ld = a.g.ld;
@@ -432,14 +431,15 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_general(SAr
     }
 }
 
-// Interior kernel: work items whose strip lies in columns [1, nx-2] and
+// Interior body: work items whose strip lies in columns [1, nx-2] and
 // whose whole stream (rows y0 - H - NS .. y1 + H + 2 NS) lies in rows
 // [2, ny-3], so no boundary rule applies and every access is in bounds
 // without checks.  Loads and stores are one vector per field through
-// buffer resources with a scalar row offset.
+// buffer resources with a scalar row offset.  `wid` is a wave-uniform
+// interior work id in [0, ns * ng).
 template <class Prec, int K, int DEPTH, int CW>
-__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SArgs<typename Prec::T> a, Decomp dc,
-                                                                               typename Prec::W w)
+__device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, const Decomp& dc, int wid,
+                                              const typename Prec::W& w)
 {
     using T = typename Prec::T;
     constexpr int R = KT<K>::R;
@@ -451,10 +451,6 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SA
     constexpr int E = CW + 2 * R;
 
     const int lane = threadIdx.x & (kWave - 1);
-    // Wave-uniform from here on: keeps the work item and the buffer
-    // resources in scalar registers.
-    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (threadIdx.x >> 6));
-    if (wid >= dc.ns * dc.ng) return;
     const int strip = dc.s_lo + wid % dc.ns;
     const int seg = dc.g_lo + wid / dc.ns;
     const int ld = a.g.ld;
@@ -569,6 +565,61 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SA
     }
 }
 
+// Wave-uniform global wave id (kept in scalar registers, so the work item
+// and the buffer resources derived from it are scalar too).
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+}
+
+template <class Prec, int K, int DEPTH, int CW>
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_general(SArgs<typename Prec::T> a, Decomp dc,
+                                                                              int nwork, typename Prec::W w)
+{
+    const int wid = wave_id();
+    if (wid >= nwork) return;  // whole wavefronts only
+    general_body<Prec, K, DEPTH, CW>(a, dc, wid, w);
+}
+
+template <class Prec, int K, int DEPTH, int CW>
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SArgs<typename Prec::T> a, Decomp dc,
+                                                                               typename Prec::W w)
+{
+    const int wid = wave_id();
+    if (wid >= dc.ns * dc.ng) return;
+    interior_body<Prec, K, DEPTH, CW>(a, dc, wid, w);
+}
+
+// Batched kernels: one launch advances many instances (different grids,
+// weights and buffers) by one pass.  The work items of all instances form
+// one index space; prefix[k] is the first global work id of item k and
+// prefix[count] the total.  Each wave finds its item by binary search and
+// runs the same body as the single-instance kernels.
+template <class Prec>
+struct BatchItem {
+    SArgs<typename Prec::T> a;
+    Decomp dc;
+    typename Prec::W w;
+};
+
+template <class Prec, int K, int DEPTH, int CW, bool INTERIOR>
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const BatchItem<Prec>* __restrict__ items,
+                                                                            const int* __restrict__ prefix, int count)
+{
+    const int gw = wave_id();
+    if (gw >= prefix[count]) return;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= gw) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchItem<Prec>& it = items[lo];
+    const int wid = gw - prefix[lo];
+    if constexpr (INTERIOR) interior_body<Prec, K, DEPTH, CW>(it.a, it.dc, wid, it.w);
+    else general_body<Prec, K, DEPTH, CW>(it.a, it.dc, wid, it.w);
+}
+
 template <int R, int DEPTH, int CW>
 Decomp make_decomp(const Grid& g, int rows)
 {
@@ -681,6 +732,135 @@ bool stream_depth_supported(int depth)
 }
 
 int stream_columns_per_wave(int) { return kWave * 2; }
+
+namespace {
+
+template <class Prec, int K, int DEPTH>
+void tables_depth(int rows, const std::vector<BatchInst>& insts, BatchTables& gen, BatchTables& inr)
+{
+    using T = typename Prec::T;
+    constexpr int CW = 2;
+    constexpr int R = KT<K>::R;
+    gen.prefix.assign(1, 0);
+    inr.prefix.assign(1, 0);
+    gen.items.clear();
+    inr.items.clear();
+    gen.count = inr.count = 0;
+    for (const BatchInst& in : insts) {
+        BatchItem<Prec> it{};
+        it.a.g = in.g;
+        it.a.rows = rows;
+        it.a.in_w0 = (const T*)in.in_w0;
+        it.a.in_w1 = (const T*)in.in_w1;
+        it.a.in_p = (const T*)in.in_p;
+        it.a.out_w0 = (T*)in.out_w0;
+        it.a.out_w1 = (T*)in.out_w1;
+        it.a.out_p = (T*)in.out_p;
+        it.dc = make_decomp<R, DEPTH, CW>(in.g, rows);
+        it.a.nstrips = it.dc.nstrips;
+        it.a.nwork = it.dc.nstrips * it.dc.nseg;
+        if constexpr (Prec::NW == 1) it.w = in.w64;
+        else it.w = in.w32;
+        const int ni = it.dc.ns * it.dc.ng;
+        const int nb = it.a.nwork - ni;
+        const unsigned char* raw = reinterpret_cast<const unsigned char*>(&it);
+        if (nb > 0) {
+            gen.items.insert(gen.items.end(), raw, raw + sizeof(it));
+            gen.prefix.push_back(gen.prefix.back() + nb);
+            ++gen.count;
+        }
+        if (ni > 0) {
+            inr.items.insert(inr.items.end(), raw, raw + sizeof(it));
+            inr.prefix.push_back(inr.prefix.back() + ni);
+            ++inr.count;
+        }
+    }
+}
+
+template <class Prec, int K>
+void tables_kind(int depth, int rows, const std::vector<BatchInst>& insts, BatchTables& gen, BatchTables& inr)
+{
+    switch (depth) {
+    case 1: tables_depth<Prec, K, 1>(rows, insts, gen, inr); break;
+    case 2: tables_depth<Prec, K, 2>(rows, insts, gen, inr); break;
+    case 3: tables_depth<Prec, K, 3>(rows, insts, gen, inr); break;
+    case 4: tables_depth<Prec, K, 4>(rows, insts, gen, inr); break;
+    case 6: tables_depth<Prec, K, 6>(rows, insts, gen, inr); break;
+    case 8: tables_depth<Prec, K, 8>(rows, insts, gen, inr); break;
+    default: break;
+    }
+}
+
+template <class Prec>
+void tables_prec(int kind, int depth, int rows, const std::vector<BatchInst>& insts, BatchTables& gen,
+                 BatchTables& inr)
+{
+    switch (kind) {
+    case KIND5: tables_kind<Prec, KIND5>(depth, rows, insts, gen, inr); break;
+    case KIND9: tables_kind<Prec, KIND9>(depth, rows, insts, gen, inr); break;
+    case KIND13: tables_kind<Prec, KIND13>(depth, rows, insts, gen, inr); break;
+    default: break;
+    }
+}
+
+template <class Prec, int K, int DEPTH>
+hipError_t blaunch(bool interior, const void* items, const int* prefix, int count, int total, hipStream_t s)
+{
+    const int blocks = (total + kWavesPerBlock - 1) / kWavesPerBlock;
+    const BatchItem<Prec>* it = (const BatchItem<Prec>*)items;
+    if (interior) k_stream_batch<Prec, K, DEPTH, 2, true><<<blocks, kWave * kWavesPerBlock, 0, s>>>(it, prefix, count);
+    else k_stream_batch<Prec, K, DEPTH, 2, false><<<blocks, kWave * kWavesPerBlock, 0, s>>>(it, prefix, count);
+    return hipGetLastError();
+}
+
+template <class Prec, int K>
+hipError_t blaunch_kind(int depth, bool interior, const void* items, const int* prefix, int count, int total,
+                        hipStream_t s)
+{
+    switch (depth) {
+    case 1: return blaunch<Prec, K, 1>(interior, items, prefix, count, total, s);
+    case 2: return blaunch<Prec, K, 2>(interior, items, prefix, count, total, s);
+    case 3: return blaunch<Prec, K, 3>(interior, items, prefix, count, total, s);
+    case 4: return blaunch<Prec, K, 4>(interior, items, prefix, count, total, s);
+    case 6: return blaunch<Prec, K, 6>(interior, items, prefix, count, total, s);
+    case 8: return blaunch<Prec, K, 8>(interior, items, prefix, count, total, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Prec>
+hipError_t blaunch_prec(int kind, int depth, bool interior, const void* items, const int* prefix, int count,
+                        int total, hipStream_t s)
+{
+    switch (kind) {
+    case KIND5: return blaunch_kind<Prec, KIND5>(depth, interior, items, prefix, count, total, s);
+    case KIND9: return blaunch_kind<Prec, KIND9>(depth, interior, items, prefix, count, total, s);
+    case KIND13: return blaunch_kind<Prec, KIND13>(depth, interior, items, prefix, count, total, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t batch_item_size(int precision)
+{
+    return precision == 0 ? sizeof(BatchItem<PF64>) : sizeof(BatchItem<PF32C>);
+}
+
+void batch_tables(int precision, int kind, int depth, int rows, const std::vector<BatchInst>& insts, BatchTables& gen,
+                  BatchTables& inr)
+{
+    if (precision == 0) tables_prec<PF64>(kind, depth, rows, insts, gen, inr);
+    else tables_prec<PF32C>(kind, depth, rows, insts, gen, inr);
+}
+
+hipError_t batch_launch(int precision, int kind, int depth, bool interior, const void* d_items, const int* d_prefix,
+                        int count, int total, hipStream_t s)
+{
+    if (count <= 0 || total <= 0) return hipSuccess;
+    if (precision == 0) return blaunch_prec<PF64>(kind, depth, interior, d_items, d_prefix, count, total, s);
+    return blaunch_prec<PF32C>(kind, depth, interior, d_items, d_prefix, count, total, s);
+}
 
 hipError_t stream_step_f64(const Grid& g, int kind, const StepW64& w, const StreamShape& sh, const double* p_in,
                            const double* c_in, double* p_out, double* c_out, hipStream_t s)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "point.h"
 
@@ -68,6 +69,36 @@ hipError_t stream_step_f64(const Grid& g, int kind, const StepW64& w, const Stre
 hipError_t stream_step_f32c(const Grid& g, int kind, const StepW32& w, const StreamShape& sh, const float* u,
                             const float* lo, const float* d, float* u2, float* lo2, float* d2, hipStream_t s);
 bool stream_depth_supported(int depth);
+
+// ---- batched passes (stream.hip) ----------------------------------------------
+// One instance's part of a batched pass: its grid, stencil class, input and
+// output state (FP64: window field u^k, point field u^{k-1}; compensated:
+// u, lo and d) and weights.
+struct BatchInst {
+    Grid g;
+    int kind;
+    const void* in_w0;
+    const void* in_w1;
+    const void* in_p;
+    void* out_w0;
+    void* out_w1;
+    void* out_p;
+    StepW32 w32;
+    StepW64 w64;
+};
+// Host staging of the device tables of one batched launch.
+struct BatchTables {
+    std::vector<unsigned char> items;
+    std::vector<int> prefix;  // prefix[k] = first work id of item k; back() = total
+    int count = 0;
+};
+size_t batch_item_size(int precision);
+// Tables of one pass at `depth` for the instances (all of stencil class
+// `kind`): boundary items into gen, interior items into inr.
+void batch_tables(int precision, int kind, int depth, int rows, const std::vector<BatchInst>& insts, BatchTables& gen,
+                  BatchTables& inr);
+hipError_t batch_launch(int precision, int kind, int depth, bool interior, const void* d_items, const int* d_prefix,
+                        int count, int total, hipStream_t s);
 int stream_columns_per_wave(int precision);
 
 // ---- reductions (norms.hip) -------------------------------------------------
