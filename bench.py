@@ -41,6 +41,7 @@ def parse():
                     help="summarize: directory holding the rocprofv3 csv output")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-launches", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-instance workload")
     return ap.parse_args()
 
 
@@ -167,6 +168,57 @@ def summarize(prof_dir):
     print(json.dumps(rec))
 
 
+def batch_bench(args):
+    """The batched workload: 512 seeded instances (sides log-uniform in
+    [64, 2048], schemes uniform over 5/9/13-point, lambda in [0.3, 0.9] x
+    limit, 100-2000 levels, 8 random sine modes), compensated FP32, launch
+    shapes autotuned per scheme, the whole batch replayed as one graph."""
+    import torch
+
+    import paper_1904_04048_amd as w
+    from paper_1904_04048_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    tuned = {}
+    for sch in (w.P5, w.P9, w.P13):
+        tuned[sch] = w.wave2d_autotune(w.F32C, sch, 1025, 1025)
+    probs = W.c4()
+    insts = []
+    for pr in probs:
+        U0, V0 = W.sine_series_torch(pr.nx, pr.ny, pr.modes, dev)
+        u = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device=dev)
+        insts.append(dict(nx=pr.nx, ny=pr.ny, h=pr.h, tau=pr.tau, c=pr.c, scheme=pr.scheme, steps=pr.steps,
+                          flags=0, u0=U0, v0=V0, u=u, lo=torch.empty_like(u), d=torch.empty_like(u)))
+    b = w.wave2d_batch_create(insts, w.BATCH_GRAPH)
+    try:
+        st = w.wave2d_batch_stats_get(b)
+        w.wave2d_batch_run(b)  # captures the graph, warms up
+        torch.cuda.synchronize()
+        reps = max(1, min(3, args.steps))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            w.wave2d_batch_run(b)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        # Accuracy on a sample: every 64th instance against its FP64 GPU solve.
+        worst = 0.0
+        for k in range(0, len(insts), 64):
+            t = insts[k]
+            P = torch.empty_like(t["u0"])
+            C = torch.empty_like(t["u0"])
+            w.wave2d_run(t["u0"], t["v0"], P, C, t["h"], t["tau"], t["c"], t["scheme"], t["steps"])
+            nr = w.wave2d_f32c_norms(t["u"], t["lo"], C)
+            worst = max(worst, nr[0] / nr[1])
+    finally:
+        w.wave2d_batch_destroy(b)
+    return {"workload": "512 instances, sides 64-2048, schemes 5/9/13, 100-2000 levels, compensated FP32",
+            "value": round(st["lup"] / dt / 1e9, 2), "unit": "GLUP/s", "ms_per_batch": round(dt * 1e3, 2),
+            "lup": st["lup"], "rounds": st["rounds"], "launches_per_run": st["launches"],
+            "state_bytes": st["state_bytes"], "graph": True,
+            "tuned_shapes": {str(k): list(v) for k, v in tuned.items()},
+            "max_rel_err_vs_gpu_fp64_sampled": worst, "sample": "every 64th instance"}
+
+
 def main():
     args = parse()
     if args.mode == "summarize":
@@ -273,6 +325,10 @@ def main():
                       "depth": w.wave2d_get_tuning(w.F64, p.scheme, p.nx, p.ny)[0]},
         "roofline": roofline,
     }
+    if not args.no_batch:
+        del u, lo, d, work, work64, UP, UC, U_ex
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, u0, v0)
     print(json.dumps(out), flush=True)

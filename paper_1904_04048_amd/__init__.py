@@ -17,7 +17,7 @@ import ctypes
 
 from . import _lib
 from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13,
-                   BatchStats, Instance, Tuning, Wave2dError)
+                   BatchStats, Instance, Request, Result, ServerStats, Tuning, Wave2dError)
 
 __all__ = [
     "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE",
@@ -25,7 +25,8 @@ __all__ = [
     "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
     "wave2d_release", "wave2d_autotune", "wave2d_batch_create", "wave2d_batch_run", "wave2d_batch_stats_get",
-    "wave2d_batch_destroy", "BATCH_GRAPH",
+    "wave2d_batch_destroy", "BATCH_GRAPH", "wave2d_sine_series", "wave2d_server_create", "wave2d_server_submit",
+    "wave2d_server_poll", "wave2d_server_release", "wave2d_server_stats_get", "wave2d_server_destroy",
 ]
 
 
@@ -207,3 +208,74 @@ def wave2d_batch_stats_get(batch):
 
 def wave2d_batch_destroy(batch):
     _lib.check(_lib.load().wave2d_batch_destroy(batch))
+
+
+def wave2d_sine_series(u0, v0, modes):
+    """Sample u0, v0 (float64 GPU grids) from modes [(p, q, A, B), ...] on the device."""
+    import torch
+    nx, ny, ld, s = _grid(u0, v0, dtypes=(torch.float64,) * 2)
+    arr = (ctypes.c_double * (4 * len(modes)))(*[float(v) for m in modes for v in m])
+    _lib.check(_lib.load().wave2d_sine_series(nx, ny, ld, len(modes), arr, _p(u0), _p(v0), s))
+
+
+def wave2d_server_create(mem_budget: int = 0, flags: int = 0):
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().wave2d_server_create(mem_budget, flags, ctypes.byref(h)))
+    return h
+
+
+def wave2d_server_submit(server, nx, ny, h, tau, c, scheme, steps, flags=0, modes=None, u0=None, v0=None):
+    """Queue a request; initial data as sine modes [(p, q, A, B), ...] or as
+    GPU float64 grids u0, v0 (kept alive by the caller until completion)."""
+    rq = Request(nx, ny, h, tau, c, scheme, flags, steps, 0, None, None, None)
+    keep = None
+    if modes:
+        keep = (ctypes.c_double * (4 * len(modes)))(*[float(v) for m in modes for v in m])
+        rq.nmodes = len(modes)
+        rq.modes = ctypes.cast(keep, ctypes.c_void_p)
+    else:
+        rq.u0 = u0.data_ptr() if u0 is not None else None
+        rq.v0 = v0.data_ptr() if v0 is not None else None
+    rid = ctypes.c_uint64()
+    _lib.check(_lib.load().wave2d_server_submit(server, ctypes.byref(rq), ctypes.byref(rid)))
+    return rid.value
+
+
+def wave2d_server_poll(server, rid):
+    """None while the request is queued or running, else a dict."""
+    r = Result()
+    st = _lib.load().wave2d_server_poll(server, rid, ctypes.byref(r))
+    if st == _lib.EBUSY:
+        return None
+    _lib.check(st)
+    return {k: getattr(r, k) for k, _ in Result._fields_}
+
+
+def wave2d_server_release(server, rid):
+    _lib.check(_lib.load().wave2d_server_release(server, rid))
+
+
+def wave2d_server_stats_get(server):
+    s = ServerStats()
+    _lib.check(_lib.load().wave2d_server_stats_get(server, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+
+def wave2d_server_destroy(server):
+    _lib.check(_lib.load().wave2d_server_destroy(server))
+
+
+def result_tensor(res):
+    """View a served FP64 result (device pointer owned by the server until
+    release) as a torch tensor copy."""
+    import torch
+    n = res["ld"] * res["ny"]
+    buf = torch.empty(n, dtype=torch.float64, device="cuda")
+    _lib.load()
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    rc = hip.hipMemcpy(C.c_void_p(buf.data_ptr()), C.c_void_p(res["u"]), n * 8, 3)  # device to device
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return buf.view(res["ny"], res["ld"])[:, :res["nx"]]

@@ -42,6 +42,24 @@ class BatchStats(ctypes.Structure):
                 ("lup", ctypes.c_int64), ("state_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("h", ctypes.c_double), ("tau", ctypes.c_double),
+                ("c", ctypes.c_double), ("scheme", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("steps", ctypes.c_int64), ("nmodes", ctypes.c_int32), ("modes", ctypes.c_void_p),
+                ("u0", ctypes.c_void_p), ("v0", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("u", ctypes.c_void_p), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "failed", "active", "queued",
+                                              "quanta", "lup_done", "bytes_in_use", "bytes_budget")]
+
+
 _SIGS = {
     "wave2d_lambda_max": (D, [I]),
     "wave2d_weights": (I, [I, U32, D, P, P, P]),
@@ -65,6 +83,13 @@ _SIGS = {
     "wave2d_batch_run": (I, [P, P]),
     "wave2d_batch_stats_get": (I, [P, P]),
     "wave2d_batch_destroy": (I, [P]),
+    "wave2d_sine_series": (I, [I64, I64, I64, ctypes.c_int32, P, P, P, P]),
+    "wave2d_server_create": (I, [SZ, U32, P]),
+    "wave2d_server_submit": (I, [P, P, P]),
+    "wave2d_server_poll": (I, [P, ctypes.c_uint64, P]),
+    "wave2d_server_release": (I, [P, ctypes.c_uint64]),
+    "wave2d_server_stats_get": (I, [P, P]),
+    "wave2d_server_destroy": (I, [P]),
 }
 
 _lib = None

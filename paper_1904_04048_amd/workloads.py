@@ -48,6 +48,22 @@ def sine_series(nx: int, ny: int, modes: List[Mode]):
     return u0, v0
 
 
+def sine_series_torch(nx: int, ny: int, modes: List[Mode], device):
+    """sine_series sampled on the GPU (float64 tensors of shape (ny, nx))."""
+    import torch
+    x = torch.arange(nx, dtype=torch.float64, device=device)
+    y = torch.arange(ny, dtype=torch.float64, device=device)
+    u0 = torch.zeros((ny, nx), dtype=torch.float64, device=device)
+    v0 = torch.zeros_like(u0)
+    for (p, q, A, B) in modes:
+        e = torch.outer(torch.sin(q * math.pi * y / (ny - 1)), torch.sin(p * math.pi * x / (nx - 1)))
+        if A:
+            u0.add_(e, alpha=A)
+        if B:
+            v0.add_(e, alpha=B)
+    return u0, v0
+
+
 def smooth_step(t):
     """C-infinity blend from 0 (t <= 0) to 1 (t >= 1)."""
     t = np.clip(np.asarray(t, dtype=np.float64), 0.0, 1.0)
