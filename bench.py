@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-launches", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-instance workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
+    ap.add_argument("--serve-requests", type=int, default=300)
     return ap.parse_args()
 
 
@@ -219,6 +221,95 @@ def batch_bench(args):
             "max_rel_err_vs_gpu_fp64_sampled": worst, "sample": "every 64th instance"}
 
 
+def serve_bench(args):
+    """Served workload: requests drawn like the batch (sides up to 4096,
+    100-5000 levels), arriving as a Poisson process at 70% of the server's
+    measured saturation throughput; latency = completion - submission."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1904_04048_amd as w
+    from paper_1904_04048_amd import workloads as W
+
+    n_meas = args.serve_requests
+    n_warm = 16
+    probs = W.c5_requests(n_warm + n_meas + 64)
+    sv = w.wave2d_server_create(48 << 30)
+    try:
+        def submit(pr):
+            return w.wave2d_server_submit(sv, pr.nx, pr.ny, pr.h, pr.tau, pr.c, pr.scheme, pr.steps, modes=pr.modes)
+
+        def drain(ids):
+            out = {}
+            while len(out) < len(ids):
+                for i in ids:
+                    if i not in out:
+                        r = w.wave2d_server_poll(sv, i)
+                        if r is not None:
+                            out[i] = r
+                time.sleep(0.0005)
+            return out
+
+        # Saturation: a burst of requests submitted at once.
+        burst = probs[-64:]
+        t0 = time.perf_counter()
+        ids = [submit(pr) for pr in burst]
+        drain(ids)
+        sat = sum(pr.lup for pr in burst) / (time.perf_counter() - t0) / 1e9
+        for i in ids:
+            w.wave2d_server_release(sv, i)
+        mean_lup = float(np.mean([pr.lup for pr in probs[:n_warm + n_meas]]))
+        qps = 0.7 * sat * 1e9 / mean_lup
+        arrivals = W.poisson_arrivals(n_warm + n_meas, qps)
+        sub_ids = [None] * len(arrivals)
+        start = time.perf_counter()
+
+        def client():
+            for k, t in enumerate(arrivals):
+                dt = start + t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                sub_ids[k] = submit(probs[k])
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        res = drain(sub_ids)
+        makespan = time.perf_counter() - start
+        meas = [res[sub_ids[k]] for k in range(n_warm, len(sub_ids))]
+        lat = np.array([r["t_done"] - r["t_submit"] for r in meas])
+        t_first = min(r["t_submit"] for r in meas)
+        t_last = max(r["t_done"] for r in meas)
+        lup_meas = sum(probs[k].lup for k in range(n_warm, len(sub_ids)))
+        # Error on a sample: served result against the FP64 GPU solve.
+        worst = 0.0
+        for k in range(n_warm, len(sub_ids), 50):
+            pr = probs[k]
+            U0 = torch.empty((pr.ny, pr.nx), dtype=torch.float64, device="cuda")
+            V0 = torch.empty_like(U0)
+            w.wave2d_sine_series(U0, V0, pr.modes)
+            P, C = torch.empty_like(U0), torch.empty_like(U0)
+            w.wave2d_run(U0, V0, P, C, pr.h, pr.tau, pr.c, pr.scheme, pr.steps)
+            got = w.result_tensor(res[sub_ids[k]])
+            nr = w.wave2d_norms(got.contiguous(), C)
+            worst = max(worst, nr[0] / nr[1])
+        st = w.wave2d_server_stats_get(sv)
+        for i in sub_ids:
+            w.wave2d_server_release(sv, i)
+    finally:
+        w.wave2d_server_destroy(sv)
+    return {"workload": "Poisson arrivals of requests: sides 64-4096, schemes 5/9/13, 100-5000 levels, "
+                        "compensated FP32, FP64 results",
+            "requests": n_meas, "warmup_requests": n_warm, "qps": round(qps, 2),
+            "saturation_glups": round(sat, 1), "value": round(lup_meas / (t_last - t_first) / 1e9, 1),
+            "unit": "GLUP/s", "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "mean_ms": round(float(lat.mean()) * 1e3, 2), "makespan_s": round(makespan, 2),
+            "quanta": st["quanta"], "max_rel_err_vs_gpu_fp64_sampled": worst, "sample": "every 50th request"}
+
+
 def main():
     args = parse()
     if args.mode == "summarize":
@@ -329,6 +420,9 @@ def main():
         del u, lo, d, work, work64, UP, UC, U_ex
         torch.cuda.empty_cache()
         out["batch"] = batch_bench(args)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = serve_bench(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, u0, v0)
     print(json.dumps(out), flush=True)
