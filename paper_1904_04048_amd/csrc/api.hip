@@ -203,9 +203,15 @@ TuneEntry g_tune[2][4] = {};
 wave2d_tuning default_tuning(int precision, int scheme, int64_t, int64_t)
 {
     wave2d_tuning t;
-    t.rows = 16;
-    t.depth = (scheme == WAVE2D_P13) ? 3 : 6;
-    if (precision == WAVE2D_F64 && (scheme == WAVE2D_P9 || scheme == WAVE2D_C9)) t.rows = 24;
+    if (precision == WAVE2D_F32C) {
+        if (scheme == WAVE2D_P13) t = wave2d_tuning{3, 16};
+        else if (scheme == WAVE2D_P5) t = wave2d_tuning{8, 32};
+        else t = wave2d_tuning{6, 32};
+    } else {
+        if (scheme == WAVE2D_P13) t = wave2d_tuning{3, 16};
+        else if (scheme == WAVE2D_P5) t = wave2d_tuning{6, 16};
+        else t = wave2d_tuning{6, 24};
+    }
     return t;
 }
 

@@ -176,6 +176,156 @@ __device__ __forceinline__ void row_update(
     }
 }
 
+// The same update from rows that hold only the lane's own CW columns: the
+// neighbours beyond them are fetched from the adjacent lanes where they are
+// used (a DPP shift that the compiler folds into the subtraction or
+// addition consuming it, for single precision).  Same arithmetic, fewer
+// registers than keeping extended rows.
+template <class Prec, int K, int CW>
+__device__ __forceinline__ void row_update_at_use(
+    const typename Prec::T (&Wc)[Prec::NW][CW], const typename Prec::T (&Wn)[Prec::NW][CW],
+    const typename Prec::T (&Ws)[Prec::NW][CW], const typename Prec::T (&Wnn)[Prec::NW][CW],
+    const typename Prec::T (&Wss)[Prec::NW][CW], const typename Prec::T (&Pin)[CW], const typename Prec::W& w,
+    typename Prec::T (&nv)[Prec::NW][CW], typename Prec::T (&np)[CW])
+{
+    using T = typename Prec::T;
+    constexpr int NW = Prec::NW;
+    // column m + o of a row, o in [-2, 2]
+    auto col = [](const T (&r)[CW], int m, int o) -> T {
+        const int c = m + o;
+        if (c >= 0 && c < CW) return r[c];
+        if (c >= CW) return from_right(r[c - CW]);
+        return from_left(r[c + CW]);
+    };
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        Nbh<T> nb[NW];
+#pragma unroll
+        for (int f = 0; f < NW; ++f) {
+            nb[f].C = Wc[f][m];
+            nb[f].E = col(Wc[f], m, 1);
+            nb[f].W = col(Wc[f], m, -1);
+            nb[f].N = Wn[f][m];
+            nb[f].S = Ws[f][m];
+            if constexpr (KT<K>::DIAG) {
+                nb[f].NE = col(Wn[f], m, 1);
+                nb[f].NW = col(Wn[f], m, -1);
+                nb[f].SE = col(Ws[f], m, 1);
+                nb[f].SW = col(Ws[f], m, -1);
+            } else {
+                nb[f].NE = nb[f].NW = nb[f].SE = nb[f].SW = T(0);
+            }
+            if constexpr (KT<K>::AX2) {
+                nb[f].EE = col(Wc[f], m, 2);
+                nb[f].WW = col(Wc[f], m, -2);
+                nb[f].NN = Wnn[f][m];
+                nb[f].SS = Wss[f][m];
+            } else {
+                nb[f].EE = nb[f].WW = nb[f].NN = nb[f].SS = T(0);
+            }
+        }
+        if constexpr (NW == 1) {
+            const T s = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
+            nv[0][m] = (T)f64_update((double)nb[0].C, (double)Pin[m], (double)s);
+            np[m] = nb[0].C;
+        } else {
+            const float su = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
+            const float sl = lap_sum<K>(nb[1], w.wc, w.w10, w.w11, w.w20);
+            float u2, l2, d2;
+            f32c_update(su, sl, nb[0].C, nb[1].C, Pin[m], u2, l2, d2);
+            nv[0][m] = u2;
+            nv[1][m] = l2;
+            np[m] = d2;
+        }
+    }
+}
+
+// Compensated single precision with differences carried from row to row.
+// Going down the rows of one level, the centre row y reuses what row y-1
+// computed: S - C = -(N - C of row y-1), SW - C and SE - C are the negated
+// NE - C and NW - C of row y-1 one column over, and the lo row sums
+// lo(i+1) + lo(i-1) of rows y-1 and y.  Every operation and its operands
+// are those of lap_diff / lap_sum (a + (-b) rounds exactly as a - b), so
+// the result is bit-identical; only repeated subtractions are saved.
+template <int CW>
+struct Carry {
+    float dv[CW];  // N - C of the previous centre row
+    float dd[CW];  // NE - C of the previous centre row
+    float da[CW];  // NW - C of the previous centre row
+    float hs0[CW]; // lo(i+1) + lo(i-1) of row y-1
+    float hs1[CW]; // lo(i+1) + lo(i-1) of row y
+};
+
+template <int K, int CW>
+__device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const float (&Wn)[2][CW],
+                                                 const float (&Ws)[2][CW], const float (&Wnn)[2][CW],
+                                                 const float (&Wss)[2][CW], const float (&Pin)[CW], Carry<CW>& cr,
+                                                 const StepW32& w, bool update, float (&nv)[2][CW], float (&np)[CW])
+{
+    auto col = [](const float (&r)[CW], int m, int o) -> float {
+        const int c = m + o;
+        if (c >= 0 && c < CW) return r[c];
+        if (c >= CW) return from_right(r[c - CW]);
+        return from_left(r[c + CW]);
+    };
+    const float(&U)[CW] = Wc[0];
+    const float(&Un)[CW] = Wn[0];
+    // Quantities of this centre row that the next row reuses.
+    float dv[CW], dd[CW], da[CW], hsn[CW];
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        dv[m] = Un[m] - U[m];
+        if constexpr (KT<K>::DIAG) {
+            dd[m] = col(Un, m, 1) - U[m];
+            da[m] = col(Un, m, -1) - U[m];
+            hsn[m] = col(Wn[1], m, 1) + col(Wn[1], m, -1);
+        } else {
+            dd[m] = da[m] = 0.f;
+            hsn[m] = col(Wn[1], m, 1) + col(Wn[1], m, -1);
+        }
+    }
+    if (update) {
+        // eh[k] = u(k) - u(k-1) for the centre row, k = 0..CW (relative columns).
+        float eh[CW + 1];
+        eh[0] = U[0] - col(U, 0, -1);
+#pragma unroll
+        for (int k = 1; k < CW; ++k) eh[k] = U[k] - U[k - 1];
+        eh[CW] = col(U, CW - 1, 1) - U[CW - 1];
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            const float C = U[m];
+            float s = w.w10 * ((eh[m + 1] - eh[m]) + (dv[m] - cr.dv[m]));
+            if constexpr (KT<K>::DIAG) {
+                const float sw = (m >= 1) ? cr.dd[m - 1] : from_left(cr.dd[CW - 1]);
+                const float se = (m + 1 < CW) ? cr.da[m + 1] : from_right(cr.da[0]);
+                s = fmaT(w.w11, (dd[m] - sw) + (da[m] - se), s);
+            }
+            if constexpr (KT<K>::AX2) {
+                s = fmaT(w.w20, ((col(U, m, 2) - C) + (col(U, m, -2) - C)) + ((Wnn[0][m] - C) + (Wss[0][m] - C)), s);
+            }
+            // lo part (weighted sums)
+            const float Lc = Wc[1][m];
+            float sl = fmaT(w.w10, cr.hs1[m] + (Wn[1][m] + Ws[1][m]), w.wc * Lc);
+            if constexpr (KT<K>::DIAG) sl = fmaT(w.w11, hsn[m] + cr.hs0[m], sl);
+            if constexpr (KT<K>::AX2)
+                sl = fmaT(w.w20, (col(Wc[1], m, 2) + col(Wc[1], m, -2)) + (Wnn[1][m] + Wss[1][m]), sl);
+            float u2, l2, d2;
+            f32c_update(s, sl, C, Lc, Pin[m], u2, l2, d2);
+            nv[0][m] = u2;
+            nv[1][m] = l2;
+            np[m] = d2;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        cr.dv[m] = dv[m];
+        cr.dd[m] = dd[m];
+        cr.da[m] = da[m];
+        cr.hs0[m] = cr.hs1[m];
+        cr.hs1[m] = hsn[m];
+    }
+}
+
 // Fill the R neighbour columns on each side of an extended row from the
 // adjacent lanes.
 template <typename T, int NW, int CW, int R>
@@ -448,7 +598,12 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
     constexpr int H = R * DEPTH;
     constexpr int HP = halo_cols<R, DEPTH>();
     constexpr int SW = kWave * CW - 2 * HP;
-    constexpr int E = CW + 2 * R;
+    // Single precision keeps only the lane's own columns per row and
+    // fetches neighbours where they are used; double precision cannot fold
+    // the shifts into its arithmetic and keeps extended rows instead.
+    constexpr bool EXT = (Prec::NW == 1);
+    constexpr int E = EXT ? CW + 2 * R : CW;
+    constexpr int CB = EXT ? R : 0;  // index of the lane's first column in a row
 
     const int lane = threadIdx.x & (kWave - 1);
     const int strip = dc.s_lo + wid % dc.ns;
@@ -498,7 +653,7 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
         for (int f = 0; f < NW; ++f) {
             const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
 #pragma unroll
-            for (int m = 0; m < CW; ++m) v[f][R + m] = x.v[m];
+            for (int m = 0; m < CW; ++m) v[f][CB + m] = x.v[m];
         }
         int jp = jj - R;
         if constexpr (DEPTH == 1) {
@@ -510,21 +665,43 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
         for (int m = 0; m < CW; ++m) p[m] = x.v[m];
     };
 
+    // Differences carried down the rows of each level (single precision).
+    // They are refreshed at every row of every level, also where a level's
+    // update is skipped during the warm-up, so the first needed row of a
+    // level finds the previous row's values.
+    Carry<CW> carry[EXT ? 1 : DEPTH];
+    if constexpr (!EXT) {
+#pragma unroll
+        for (int t = 0; t < DEPTH; ++t)
+#pragma unroll
+            for (int m = 0; m < CW; ++m)
+                carry[t].dv[m] = carry[t].dd[m] = carry[t].da[m] = carry[t].hs0[m] = carry[t].hs1[m] = 0.f;
+    }
+
     auto phase = [&](int ph, int j, bool warm) {
-        extend_row<T, NW, CW, R>(win[0][ph]);
+        if constexpr (EXT) extend_row<T, NW, CW, R>(win[0][ph]);
 #pragma unroll
         for (int t = 1; t <= DEPTH; ++t) {
             if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
             const int y = j - t * R;
-            if (warm && y < y0 - (DEPTH - t) * R) continue;
+            const bool skip = warm && y < y0 - (DEPTH - t) * R;
             const int sy = mod_c(ph - t * R, NS);
             T nv[NW][E];
             T np[CW];
-            row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
-                                    win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                    win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
+            if constexpr (EXT) {
+                if (skip) continue;
+                row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
+            } else {
+                row_update_carry<K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], carry[t - 1], w, !skip,
+                                        nv, np);
+                if (skip) continue;
+            }
             if (t < DEPTH) {
-                extend_row<T, NW, CW, R>(nv);
+                if constexpr (EXT) extend_row<T, NW, CW, R>(nv);
                 T(&dst)[NW][E] = win[t][sy];
 #pragma unroll
                 for (int f = 0; f < NW; ++f)
@@ -538,7 +715,7 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
                 for (int f = 0; f < NW; ++f) {
                     Vec<T, CW> x;
 #pragma unroll
-                    for (int m = 0; m < CW; ++m) x.v[m] = nv[f][R + m];
+                    for (int m = 0; m < CW; ++m) x.v[m] = nv[f][CB + m];
                     buf_store<T, CW>(x, rs_out[f], voff, so);
                 }
                 if (a.out_p) {
