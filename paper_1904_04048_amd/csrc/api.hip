@@ -23,6 +23,9 @@ thread_local std::string g_last_error;
 
 // Largest grid side: keeps every launch grid within the hardware limits.
 constexpr int64_t kMaxSide = int64_t(1) << 18;
+// Row stride limit: the streaming kernels address a segment's rows through
+// 32-bit buffer offsets.
+constexpr int64_t kMaxLd = int64_t(1) << 22;
 
 int fail(int status, const char* fmt, ...)
 {
@@ -128,6 +131,7 @@ int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c,
     if (ld < nx) return fail(WAVE2D_EINVAL, "ld (%lld) < nx (%lld)", (long long)ld, (long long)nx);
     if (nx > kMaxSide || ny > kMaxSide)
         return fail(WAVE2D_EINVAL, "grid side exceeds %d nodes", kMaxSide);
+    if (ld > kMaxLd) return fail(WAVE2D_EINVAL, "ld (%lld) exceeds %lld", (long long)ld, (long long)kMaxLd);
     if (ld > (int64_t(1) << 31) / ny || ld * ny >= (int64_t(1) << 31))
         return fail(WAVE2D_EINVAL, "grid too large: ld*ny must be < 2^31");
     int r;
@@ -486,6 +490,7 @@ int check_grid_only(int64_t nx, int64_t ny, int64_t ld, Grid* g)
     if (nx < 1 || ny < 1) return fail(WAVE2D_EINVAL, "empty grid");
     if (nx > kMaxSide || ny > kMaxSide) return fail(WAVE2D_EINVAL, "grid side exceeds %d nodes", kMaxSide);
     if (ld < nx) return fail(WAVE2D_EINVAL, "ld (%lld) < nx (%lld)", (long long)ld, (long long)nx);
+    if (ld > kMaxLd) return fail(WAVE2D_EINVAL, "ld (%lld) exceeds %lld", (long long)ld, (long long)kMaxLd);
     if (ld * ny >= (int64_t(1) << 31)) return fail(WAVE2D_EINVAL, "grid too large: ld*ny must be < 2^31");
     *g = Grid{(int)nx, (int)ny, (int)ld};
     return WAVE2D_OK;

@@ -119,6 +119,17 @@ __device__ __forceinline__ void buf_store(const Vec<T, CW>& x, __amdgpu_buffer_r
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void buf_store1(T x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+    } else {
+        using V = unsigned __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, 0);
+    }
+}
+
 // Stencil update of one row segment (CW columns per lane) of level t from
 // the level t-1 window rows (centre, north, south, and the second ring for
 // the 13-point stencil) and the level t-1 point field.
@@ -380,9 +391,19 @@ __device__ __forceinline__ int xcd_block()
 
 // General body: any work item, boundary rule applied everywhere.  `wid`
 // is a wave-uniform boundary work id in [0, nwork).
-template <class Prec, int K, int DEPTH, int CW>
-__device__ __forceinline__ void general_body(const SArgs<typename Prec::T>& a, const Decomp& dc, int wid,
-                                             const typename Prec::W& w)
+// One body for every work item.  Interior items (BND false) have a strip
+// inside columns [1, nx-2] and a whole stream (rows y0 - H - NS ..
+// y1 + H + 2 NS) inside rows [2, ny-3]: no boundary rule applies and every
+// access is in bounds without checks.  Boundary items (BND true) apply the
+// rule after every level: rows outside [1, ny-2] are never loaded and are
+// set by the rule (a wave-uniform test per row), and on strips that reach
+// column 0 or nx-1 the columns outside [1, nx-2] are replaced (per-lane
+// selects).  Loads and stores are one vector per field through buffer
+// resources with a scalar row offset.  `wid` is a wave-uniform work id of
+// the item's class.
+template <class Prec, int K, int DEPTH, int CW, bool BND>
+__device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, const Decomp& dc, int wid,
+                                            const typename Prec::W& w)
 {
     using T = typename Prec::T;
     constexpr int R = KT<K>::R;
@@ -391,54 +412,50 @@ __device__ __forceinline__ void general_body(const SArgs<typename Prec::T>& a, c
     constexpr int H = R * DEPTH;   // rows / columns a pass reaches beyond its outputs
     constexpr int HP = halo_cols<R, DEPTH>();
     constexpr int SW = kWave * CW - 2 * HP;
-    constexpr int E = CW + 2 * R;  // extended row: R neighbours each side
+    // Single precision keeps only the lane's own columns per row and
+    // fetches neighbours where they are used; double precision cannot fold
+    // the shifts into its arithmetic and keeps extended rows instead.
+    constexpr bool EXT = (Prec::NW == 1);
+    constexpr int E = EXT ? CW + 2 * R : CW;
+    constexpr int CB = EXT ? R : 0;  // index of the lane's first column in a row
+    // Column pairs start at even columns, so a pair that is not wholly
+    // inside [0, nx) lies wholly outside [1, nx-2].
+    static_assert(CW == 2, "boundary handling assumes column pairs");
 
     const int lane = threadIdx.x & (kWave - 1);
     int strip, seg;
-    boundary_item(dc, wid, strip, seg);
+    if constexpr (BND) {
+        boundary_item(dc, wid, strip, seg);
+    } else {
+        strip = dc.s_lo + wid % dc.ns;
+        seg = dc.g_lo + wid / dc.ns;
+    }
     const int nx = a.g.nx, ny = a.g.ny, ld = a.g.ld;
     const int x0 = strip * SW - HP;
     const int xl = x0 + lane * CW;
     const int y0 = seg * a.rows;
     const int y1 = min(y0 + a.rows, ny);
+    const bool st_lane = (xl >= x0 + HP) && (xl < x0 + HP + SW) && (!BND || xl < nx);
+    // A boundary lane whose pair is not wholly inside [0, nx) loads pair 0
+    // instead (the rule replaces all its values); the last lane of the grid
+    // may store its first column only.
+    const bool lane_in = !BND || (xl >= 0 && xl + CW <= nx);
+    const bool st_full = !BND || (xl + CW <= nx);
 
-    // Column classes of this lane's CW columns.
-    bool ld_ok[CW], st_ok[CW], zero_col[CW];
+    // Boundary rule along x (strips that reach column 0 or nx-1).
+    const bool edge = BND && (x0 <= 0 || x0 + kWave * CW - 1 >= nx - 1);
+    bool zero_col[CW], ghost[CW];
     int gsrc_lane[CW], gsrc_m[CW];
-    bool ghost[CW];
+#pragma unroll
     for (int m = 0; m < CW; ++m) {
         const int x = xl + m;
-        ld_ok[m] = (x >= 0 && x < nx);
-        st_ok[m] = (x >= x0 + HP && x < x0 + HP + SW && x < nx);
         ghost[m] = (R == 2) && (x == -1 || x == nx);
         zero_col[m] = !(x >= 1 && x <= nx - 2) && !ghost[m];
-        const int src = (x == -1) ? 1 : nx - 2;
-        const int off = src - x0;
+        const int off = ((x == -1) ? 1 : nx - 2) - x0;  // column reflected into a ghost
         gsrc_lane[m] = off / CW;
         gsrc_m[m] = off % CW;
     }
-    const bool edge = (x0 <= 0) || (x0 + kWave * CW - 1 >= nx - 1);
-
-    T win[DEPTH][NS][NW][E];
-    T pf[DEPTH][NS][CW];
-#pragma unroll
-    for (int t = 0; t < DEPTH; ++t)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-#pragma unroll
-            for (int f = 0; f < NW; ++f)
-#pragma unroll
-                for (int e = 0; e < E; ++e) win[t][s][f][e] = T(0);
-#pragma unroll
-            for (int m = 0; m < CW; ++m) pf[t][s][m] = T(0);
-        }
-
-    const T* inw[2] = {a.in_w0, a.in_w1};
-    T* outw[2] = {a.out_w0, a.out_w1};
-
-    // Boundary rule along x on a freshly produced row (centre values only).
     auto fix_columns = [&](T (&v)[NW][E]) {
-        if (!edge) return;
 #pragma unroll
         for (int f = 0; f < NW; ++f) {
             T g[CW];
@@ -449,23 +466,17 @@ __device__ __forceinline__ void general_body(const SArgs<typename Prec::T>& a, c
                 for (int mm = 0; mm < CW; ++mm) {
 #pragma unroll
                     for (int m = 0; m < CW; ++m) {
-                        const T s = __shfl(v[f][R + mm], gsrc_lane[m]);
+                        const T s = __shfl(v[f][CB + mm], gsrc_lane[m]);
                         if (gsrc_m[m] == mm) g[m] = -s;
                     }
                 }
             }
 #pragma unroll
             for (int m = 0; m < CW; ++m) {
-                if (zero_col[m]) v[f][R + m] = T(0);
-                if (ghost[m]) v[f][R + m] = g[m];
+                if (zero_col[m]) v[f][CB + m] = T(0);
+                if (ghost[m]) v[f][CB + m] = g[m];
             }
         }
-    };
-    auto zero_row = [&](T (&v)[NW][E]) {
-#pragma unroll
-        for (int f = 0; f < NW; ++f)
-#pragma unroll
-            for (int e = 0; e < E; ++e) v[f][e] = T(0);
     };
     auto neg_copy = [&](T (&dst)[NW][E], const T (&src)[NW][E]) {
 #pragma unroll
@@ -474,153 +485,14 @@ __device__ __forceinline__ void general_body(const SArgs<typename Prec::T>& a, c
             for (int e = 0; e < E; ++e) dst[f][e] = -src[f][e];
     };
 
-    constexpr bool t1_narrow = (DEPTH == 1);  // only the output region's point field is needed
-    // Loads of level-0 row jj (window fields) and of the point field at row
-    // jj - R, per element; addresses are clamped into the grid so that every
-    // load is in bounds, and values outside the wanted range become 0.
-    auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
-        const bool row_ok = (jj >= 0 && jj < ny);
-        const int jp = jj - R;
-        const bool prow_ok = t1_narrow ? (jp >= y0 && jp < y1) : (jp >= 0 && jp < ny);
-        const int jr = row_ok ? jj : 0;
-        const int jpr = prow_ok ? jp : 0;
-#pragma unroll
-        for (int m = 0; m < CW; ++m) {
-            const int xr = ld_ok[m] ? xl + m : 0;
-            const size_t o = (size_t)jr * ld + xr;
-#pragma unroll
-            for (int f = 0; f < NW; ++f) {
-                const T x = inw[f][o];
-                v[f][R + m] = (row_ok && ld_ok[m]) ? x : T(0);
-            }
-            const bool pok = prow_ok && (t1_narrow ? st_ok[m] : ld_ok[m]);
-            const T x = a.in_p[(size_t)jpr * ld + xr];
-            p[m] = pok ? x : T(0);
-        }
-    };
-
-    const int jlo = y0 - H;
-    const int jhi = y1 - 1 + H;
-    const int jA = floor_div(jlo, NS) * NS;
-    issue_loads(jA, win[0][0], pf[0][mod_c(-R, NS)]);
-
-    for (int jb = jA; jb <= jhi; jb += NS) {
-#pragma unroll
-        for (int ph = 0; ph < NS; ++ph) {
-            const int j = jb + ph;
-            // Finish level-0 row j (its loads were issued one row ago).
-            {
-                T(&v)[NW][E] = win[0][ph];
-                if (j >= 1 && j <= ny - 2) {
-                    fix_columns(v);
-                    extend_row<T, NW, CW, R>(v);
-                } else {
-                    zero_row(v);
-                }
-                if constexpr (R == 2) {
-                    if (j == 1) neg_copy(win[0][mod_c(-1, NS)], v);
-                    if (j == ny) neg_copy(v, win[0][mod_c(ph - 2, NS)]);
-                }
-            }
-            // Levels 1..DEPTH at rows j - t*R; the next row's loads go out
-            // right after level 1, whose inputs they overwrite.
-#pragma unroll
-            for (int t = 1; t <= DEPTH; ++t) {
-                if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
-                const int y = j - t * R;
-                if (y < y0 - (DEPTH - t) * R || y > y1 - 1 + (DEPTH - t) * R) continue;
-                const int sy = mod_c(ph - t * R, NS);
-                T nv[NW][E];
-                T np[CW];
-                if (y >= 1 && y <= ny - 2) {
-                    row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
-                                            win[t - 1][mod_c(ph - t * R - 1, NS)],
-                                            win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                            win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
-                    fix_columns(nv);
-                    if (edge) {
-#pragma unroll
-                        for (int m = 0; m < CW; ++m)
-                            if (zero_col[m] || ghost[m]) np[m] = T(0);
-                    }
-                } else {
-#pragma unroll
-                    for (int f = 0; f < NW; ++f)
-#pragma unroll
-                        for (int m = 0; m < CW; ++m) nv[f][R + m] = T(0);
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) np[m] = T(0);
-                }
-                if (t < DEPTH) {
-                    extend_row<T, NW, CW, R>(nv);
-                    T(&dst)[NW][E] = win[t][sy];
-#pragma unroll
-                    for (int f = 0; f < NW; ++f)
-#pragma unroll
-                        for (int e = 0; e < E; ++e) dst[f][e] = nv[f][e];
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) pf[t][sy][m] = np[m];
-                    if constexpr (R == 2) {
-                        if (y == 1) neg_copy(win[t][mod_c(ph - t * R - 2, NS)], dst);
-                        if (y == ny) neg_copy(dst, win[t][mod_c(ph - t * R - 2, NS)]);
-                    }
-                } else if (y >= y0 && y < y1) {
-                    // Output row: level DEPTH (and DEPTH-1 for FP64).
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) {
-                        if (!st_ok[m]) continue;
-                        const size_t o = (size_t)y * ld + (xl + m);
-#pragma unroll
-                        for (int f = 0; f < NW; ++f) outw[f][o] = nv[f][R + m];
-                        if (a.out_p) a.out_p[o] = np[m];
-                    }
-                }
-            }
-            if constexpr (DEPTH == 1) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
-        }
-    }
-}
-
-// Interior body: work items whose strip lies in columns [1, nx-2] and
-// whose whole stream (rows y0 - H - NS .. y1 + H + 2 NS) lies in rows
-// [2, ny-3], so no boundary rule applies and every access is in bounds
-// without checks.  Loads and stores are one vector per field through
-// buffer resources with a scalar row offset.  `wid` is a wave-uniform
-// interior work id in [0, ns * ng).
-template <class Prec, int K, int DEPTH, int CW>
-__device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, const Decomp& dc, int wid,
-                                              const typename Prec::W& w)
-{
-    using T = typename Prec::T;
-    constexpr int R = KT<K>::R;
-    constexpr int NS = 2 * R + 1;
-    constexpr int NW = Prec::NW;
-    constexpr int H = R * DEPTH;
-    constexpr int HP = halo_cols<R, DEPTH>();
-    constexpr int SW = kWave * CW - 2 * HP;
-    // Single precision keeps only the lane's own columns per row and
-    // fetches neighbours where they are used; double precision cannot fold
-    // the shifts into its arithmetic and keeps extended rows instead.
-    constexpr bool EXT = (Prec::NW == 1);
-    constexpr int E = EXT ? CW + 2 * R : CW;
-    constexpr int CB = EXT ? R : 0;  // index of the lane's first column in a row
-
-    const int lane = threadIdx.x & (kWave - 1);
-    const int strip = dc.s_lo + wid % dc.ns;
-    const int seg = dc.g_lo + wid / dc.ns;
-    const int ld = a.g.ld;
-    const int x0 = strip * SW - HP;
-    const int xl = x0 + lane * CW;
-    const int y0 = seg * a.rows;
-    const int y1 = min(y0 + a.rows, a.g.ny);
-    const bool st_lane = (xl >= x0 + HP) && (xl < x0 + HP + SW);
-
     const int jA = floor_div(y0 - H, NS) * NS;
     const int jhi = y1 - 1 + H;
     // Rows this wave touches: loads from jA - R, stores up to y1 - 1, loads
-    // up to the last iteration's next row (< jhi + NS + 1).
-    const int base_row = jA - NS;
-    const uint32_t rbytes = (uint32_t)((jhi + 2 * NS + 1 - base_row) * ld * (int)sizeof(T));
+    // up to the last iteration's next row (< jhi + NS + 1); boundary items
+    // touch rows inside [0, ny) only.  The host bounds the byte size.
+    const int base_row = BND ? max(jA - NS, 0) : jA - NS;
+    const int top_row = BND ? min(jhi + 2 * NS + 1, ny) : jhi + 2 * NS + 1;
+    const uint32_t rbytes = (uint32_t)(top_row - base_row) * (uint32_t)ld * (uint32_t)sizeof(T);
     __amdgpu_buffer_rsrc_t rs_in[2], rs_out[2];
     rs_in[0] = make_rsrc(a.in_w0 + (size_t)base_row * ld, rbytes);
     rs_in[1] = make_rsrc((NW > 1 ? a.in_w1 : a.in_w0) + (size_t)base_row * ld, rbytes);
@@ -628,7 +500,8 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
     rs_out[1] = make_rsrc((NW > 1 ? a.out_w1 : a.out_w0) + (size_t)base_row * ld, rbytes);
     const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.in_p + (size_t)base_row * ld, rbytes);
     const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc((a.out_p ? a.out_p : a.out_w0) + (size_t)base_row * ld, rbytes);
-    const uint32_t voff = (uint32_t)(xl * (int)sizeof(T));
+    const uint32_t voff = (uint32_t)((lane_in ? xl : 0) * (int)sizeof(T));
+    const uint32_t voff_st = (uint32_t)(xl * (int)sizeof(T));
     const int row_bytes = ld * (int)sizeof(T);
 
     T win[DEPTH][NS][NW][E];
@@ -645,20 +518,35 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
             for (int m = 0; m < CW; ++m) pf[t][s][m] = T(0);
         }
 
+    // Level-0 row jj (window fields) and the point field at row jj - R.
+    // Boundary rows (and rows outside the grid) are not loaded but set to 0.
     // With DEPTH 1 the point field is read only on this segment's rows and
     // output columns (it may be the array being written in place).
     auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
-        const uint32_t so = (uint32_t)((jj - base_row) * row_bytes);
+        if (!BND || (jj >= 1 && jj <= ny - 2)) {
+            const uint32_t so = (uint32_t)((jj - base_row) * row_bytes);
 #pragma unroll
-        for (int f = 0; f < NW; ++f) {
-            const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
+            for (int f = 0; f < NW; ++f) {
+                const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
 #pragma unroll
-            for (int m = 0; m < CW; ++m) v[f][CB + m] = x.v[m];
+                for (int m = 0; m < CW; ++m) v[f][CB + m] = x.v[m];
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < NW; ++f)
+#pragma unroll
+                for (int m = 0; m < CW; ++m) v[f][CB + m] = T(0);
         }
         int jp = jj - R;
         if constexpr (DEPTH == 1) {
             jp = min(max(jp, y0), y1 - 1);
             if (!st_lane) return;
+        } else if constexpr (BND) {
+            if (jp < 1 || jp > ny - 2) {
+#pragma unroll
+                for (int m = 0; m < CW; ++m) p[m] = T(0);
+                return;
+            }
         }
         const Vec<T, CW> x = buf_load<T, CW>(rs_pin, voff, (uint32_t)((jp - base_row) * row_bytes));
 #pragma unroll
@@ -667,8 +555,8 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
 
     // Differences carried down the rows of each level (single precision).
     // They are refreshed at every row of every level, also where a level's
-    // update is skipped during the warm-up, so the first needed row of a
-    // level finds the previous row's values.
+    // update is skipped (warm-up, boundary rows), so the first updated row
+    // of a level finds the previous row's values.
     Carry<CW> carry[EXT ? 1 : DEPTH];
     if constexpr (!EXT) {
 #pragma unroll
@@ -679,26 +567,54 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
     }
 
     auto phase = [&](int ph, int j, bool warm) {
+        // Finish level-0 row j (its loads went out one row ago).
+        if constexpr (BND) {
+            if (edge && j >= 1 && j <= ny - 2) fix_columns(win[0][ph]);
+        }
         if constexpr (EXT) extend_row<T, NW, CW, R>(win[0][ph]);
+        if constexpr (BND && R == 2) {
+            if (j == 1) neg_copy(win[0][mod_c(ph - 2, NS)], win[0][ph]);
+            if (j == ny) neg_copy(win[0][ph], win[0][mod_c(ph - 2, NS)]);
+        }
+        // Levels 1..DEPTH at rows j - t*R; the next row's loads go out right
+        // after level 1, whose inputs they overwrite.
 #pragma unroll
         for (int t = 1; t <= DEPTH; ++t) {
             if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
             const int y = j - t * R;
             const bool skip = warm && y < y0 - (DEPTH - t) * R;
+            const bool inside = !BND || (y >= 1 && y <= ny - 2);
             const int sy = mod_c(ph - t * R, NS);
             T nv[NW][E];
             T np[CW];
             if constexpr (EXT) {
                 if (skip) continue;
-                row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
-                                        win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
+                if (inside)
+                    row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                            win[t - 1][mod_c(ph - t * R - 1, NS)],
+                                            win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                            win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
             } else {
                 row_update_carry<K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
                                         win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], carry[t - 1], w, !skip,
-                                        nv, np);
+                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], carry[t - 1], w,
+                                        !skip && inside, nv, np);
                 if (skip) continue;
+            }
+            if constexpr (BND) {
+                if (!inside) {
+#pragma unroll
+                    for (int f = 0; f < NW; ++f)
+#pragma unroll
+                        for (int m = 0; m < CW; ++m) nv[f][CB + m] = T(0);
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) np[m] = T(0);
+                } else if (edge) {
+                    fix_columns(nv);
+#pragma unroll
+                    for (int m = 0; m < CW; ++m)
+                        if (zero_col[m] || ghost[m]) np[m] = T(0);
+                }
             }
             if (t < DEPTH) {
                 if constexpr (EXT) extend_row<T, NW, CW, R>(nv);
@@ -709,20 +625,31 @@ __device__ __forceinline__ void interior_body(const SArgs<typename Prec::T>& a, 
                     for (int e = 0; e < E; ++e) dst[f][e] = nv[f][e];
 #pragma unroll
                 for (int m = 0; m < CW; ++m) pf[t][sy][m] = np[m];
+                if constexpr (BND && R == 2) {
+                    if (y == 1) neg_copy(win[t][mod_c(ph - t * R - 2, NS)], dst);
+                    if (y == ny) neg_copy(dst, win[t][mod_c(ph - t * R - 2, NS)]);
+                }
             } else if (y >= y0 && y < y1 && st_lane) {
                 const uint32_t so = (uint32_t)((y - base_row) * row_bytes);
+                if (st_full) {
 #pragma unroll
-                for (int f = 0; f < NW; ++f) {
-                    Vec<T, CW> x;
+                    for (int f = 0; f < NW; ++f) {
+                        Vec<T, CW> x;
 #pragma unroll
-                    for (int m = 0; m < CW; ++m) x.v[m] = nv[f][CB + m];
-                    buf_store<T, CW>(x, rs_out[f], voff, so);
-                }
-                if (a.out_p) {
-                    Vec<T, CW> x;
+                        for (int m = 0; m < CW; ++m) x.v[m] = nv[f][CB + m];
+                        buf_store<T, CW>(x, rs_out[f], voff_st, so);
+                    }
+                    if (a.out_p) {
+                        Vec<T, CW> x;
 #pragma unroll
-                    for (int m = 0; m < CW; ++m) x.v[m] = np[m];
-                    buf_store<T, CW>(x, rs_pout, voff, so);
+                        for (int m = 0; m < CW; ++m) x.v[m] = np[m];
+                        buf_store<T, CW>(x, rs_pout, voff_st, so);
+                    }
+                } else {
+                    // Last lane of the grid: its first column only (xl = nx - 1).
+#pragma unroll
+                    for (int f = 0; f < NW; ++f) buf_store1<T>(nv[f][CB], rs_out[f], voff_st, so);
+                    if (a.out_p) buf_store1<T>(np[0], rs_pout, voff_st, so);
                 }
             }
         }
@@ -755,7 +682,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_general(SAr
 {
     const int wid = wave_id();
     if (wid >= nwork) return;  // whole wavefronts only
-    general_body<Prec, K, DEPTH, CW>(a, dc, wid, w);
+    stream_body<Prec, K, DEPTH, CW, true>(a, dc, wid, w);
 }
 
 template <class Prec, int K, int DEPTH, int CW>
@@ -764,7 +691,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SA
 {
     const int wid = wave_id();
     if (wid >= dc.ns * dc.ng) return;
-    interior_body<Prec, K, DEPTH, CW>(a, dc, wid, w);
+    stream_body<Prec, K, DEPTH, CW, false>(a, dc, wid, w);
 }
 
 // Batched kernels: one launch advances many instances (different grids,
@@ -793,8 +720,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const
     }
     const BatchItem<Prec>& it = items[lo];
     const int wid = gw - prefix[lo];
-    if constexpr (INTERIOR) interior_body<Prec, K, DEPTH, CW>(it.a, it.dc, wid, it.w);
-    else general_body<Prec, K, DEPTH, CW>(it.a, it.dc, wid, it.w);
+    stream_body<Prec, K, DEPTH, CW, !INTERIOR>(it.a, it.dc, wid, it.w);
 }
 
 template <int R, int DEPTH, int CW>
@@ -834,6 +760,17 @@ Decomp make_decomp(const Grid& g, int rows)
     return d;
 }
 
+// Rows per segment for a grid: a wave's buffer resources span at most
+// rows + 2H + 4NS rows of ld elements, which must stay below 2^31 bytes
+// (row strides are bounded by the grid validation, so the cap is >= 8).
+template <int R, int DEPTH>
+int fit_rows(const Grid& g, int rows, size_t elt)
+{
+    constexpr int NS = 2 * R + 1, H = R * DEPTH;
+    const long long cap = ((1LL << 31) - 1) / ((long long)g.ld * (long long)elt) - (2 * H + 4 * NS);
+    return (int)std::max<long long>(1, std::min<long long>(rows, cap));
+}
+
 template <class Prec, int K, int DEPTH>
 hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, const Fork* fork,
                         SArgs<typename Prec::T> a, hipStream_t s)
@@ -842,6 +779,7 @@ hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, cons
     constexpr int R = KT<K>::R;
     constexpr int SW = kWave * CW - 2 * halo_cols<R, DEPTH>();
     static_assert(SW > 0, "strip too narrow");
+    rows = fit_rows<R, DEPTH>(g, rows, sizeof(typename Prec::T));
     a.g = g;
     a.rows = rows;
     const Decomp dc = make_decomp<R, DEPTH, CW>(g, rows);
@@ -926,14 +864,14 @@ void tables_depth(int rows, const std::vector<BatchInst>& insts, BatchTables& ge
     for (const BatchInst& in : insts) {
         BatchItem<Prec> it{};
         it.a.g = in.g;
-        it.a.rows = rows;
+        it.a.rows = fit_rows<R, DEPTH>(in.g, rows, sizeof(T));
         it.a.in_w0 = (const T*)in.in_w0;
         it.a.in_w1 = (const T*)in.in_w1;
         it.a.in_p = (const T*)in.in_p;
         it.a.out_w0 = (T*)in.out_w0;
         it.a.out_w1 = (T*)in.out_w1;
         it.a.out_p = (T*)in.out_p;
-        it.dc = make_decomp<R, DEPTH, CW>(in.g, rows);
+        it.dc = make_decomp<R, DEPTH, CW>(in.g, it.a.rows);
         it.a.nstrips = it.dc.nstrips;
         it.a.nwork = it.dc.nstrips * it.dc.nseg;
         if constexpr (Prec::NW == 1) it.w = in.w64;

@@ -114,7 +114,7 @@ def _step(L, nx=10, ny=10, ld=10, h=0.1, tau=0.05, c=1.0, scheme=5, flags=0, ste
     (dict(c=float("nan")), -1), (dict(scheme=7), -1), (dict(flags=0x80), -1), (dict(steps=-1), -1),
     (dict(a=ctypes.c_void_p(0)), -1), (dict(b=FAKE), -1),
     (dict(tau=0.0708), -2), (dict(scheme=13, tau=0.0708), -2), (dict(scheme=9, tau=0.0797), -2),
-    (dict(nx=50000, ny=50000, ld=50000), -1),
+    (dict(nx=50000, ny=50000, ld=50000), -1), (dict(ld=(1 << 22) + 1), -1),
 ])
 def test_validation_rejects(L, kw, code):
     assert _step(L, **kw) == code
