@@ -226,6 +226,7 @@ def batch_bench(args):
             "lup": st["lup"], "rounds": st["rounds"], "launches_per_run": st["launches"],
             "state_bytes": st["state_bytes"], "graph": True,
             "tuned_shapes": {str(k): list(v) for k, v in tuned.items()},
+            "work_items": st["items"], "mean_segment_rows": round(st["item_rows"] / max(1, st["items"]), 1),
             "max_rel_err_vs_gpu_fp64_sampled": worst, "sample": "every 64th instance"}
 
 

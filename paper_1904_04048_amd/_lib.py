@@ -39,7 +39,8 @@ class Instance(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("instances", ctypes.c_int64), ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("lup", ctypes.c_int64), ("state_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64)]
+                ("lup", ctypes.c_int64), ("state_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64),
+                ("items", ctypes.c_int64), ("item_rows", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):

@@ -239,6 +239,8 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
                     const BatchTables& t = pass ? inr : gen;
                     if (t.count == 0) continue;
                     Launch L{c.kind, dep, pass == 1, 0, 0, t.count, t.prefix.back()};
+                    b->st.items += t.prefix.back();
+                    b->st.item_rows += (int64_t)t.prefix.back() * t.rows;
                     align_host();
                     L.items_off = host.size();
                     host.insert(host.end(), t.items.begin(), t.items.end());

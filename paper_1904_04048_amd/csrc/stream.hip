@@ -19,6 +19,8 @@
 // Per-node arithmetic is the same inline code as in the one-node-per-thread
 // kernels (point.h), so results are bit-identical to them for every DEPTH,
 // segment length and strip width.
+#include <cmath>
+
 #include "w2d.h"
 
 namespace w2d {
@@ -850,12 +852,60 @@ int stream_columns_per_wave(int) { return kWave * 2; }
 
 namespace {
 
+// Wave slots of the current device: every CU runs 4 SIMDs, and the
+// streaming kernels fit at least 2 waves per SIMD.
+int wave_slots()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    return cus * 4 * 2;
+}
+
+// Segment rows for one batched launch.  A work item recomputes about
+// R*(DEPTH-1) rows of its neighbours per level and streams 2R+1 rows of
+// warm-up, so its cost grows like rows + R*(DEPTH-1) + 2R+1 while it
+// produces `rows` rows; all items of a launch cost the same, so the launch
+// takes ceil(items / slots) item times.  The candidate (not below the
+// tuned floor) with the least modelled time wins: tall segments when many
+// instances share the launch, the floor when they are few.
+template <int R, int DEPTH>
+int batch_rows(int rows_min, const std::vector<BatchInst>& insts)
+{
+    constexpr int HP = halo_cols<R, DEPTH>();
+    constexpr int SW = kWave * 2 - 2 * HP;
+    static const int cand[] = {12, 16, 24, 32, 48, 64};
+    const double slots = wave_slots();
+    auto cost = [&](int r) {
+        double items = 0;
+        for (const BatchInst& in : insts)
+            items += (double)((in.g.nx + SW - 1) / SW) * (double)((in.g.ny + r - 1) / r);
+        return std::ceil(items / slots) * (r + R * (DEPTH - 1) + 2 * R + 1);
+    };
+    int best = rows_min;
+    double bc = cost(rows_min);
+    for (int r : cand) {
+        if (r <= rows_min) continue;
+        const double c = cost(r);
+        if (c < bc) {
+            bc = c;
+            best = r;
+        }
+    }
+    return best;
+}
+
 template <class Prec, int K, int DEPTH>
 void tables_depth(int rows, const std::vector<BatchInst>& insts, BatchTables& gen, BatchTables& inr)
 {
     using T = typename Prec::T;
     constexpr int CW = 2;
     constexpr int R = KT<K>::R;
+    rows = batch_rows<R, DEPTH>(rows, insts);
+    gen.rows = inr.rows = rows;
     gen.prefix.assign(1, 0);
     inr.prefix.assign(1, 0);
     gen.items.clear();

@@ -91,10 +91,13 @@ struct BatchTables {
     std::vector<unsigned char> items;
     std::vector<int> prefix;  // prefix[k] = first work id of item k; back() = total
     int count = 0;
+    int rows = 0;  // segment rows the launch uses
 };
 size_t batch_item_size(int precision);
 // Tables of one pass at `depth` for the instances (all of stencil class
-// `kind`): boundary items into gen, interior items into inr.
+// `kind`): boundary items into gen, interior items into inr.  `rows` is the
+// least segment height; taller segments are taken where the launch still
+// has enough work items to fill the GPU (see batch_rows in stream.hip).
 void batch_tables(int precision, int kind, int depth, int rows, const std::vector<BatchInst>& insts, BatchTables& gen,
                   BatchTables& inr);
 hipError_t batch_launch(int precision, int kind, int depth, bool interior, const void* d_items, const int* d_prefix,

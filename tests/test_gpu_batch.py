@@ -74,6 +74,30 @@ def test_batch_bitwise_equals_solo(graph):
         w.wave2d_batch_destroy(b)
 
 
+def test_batch_tall_segments_bitwise():
+    # Enough work items per launch that taller segments than the tuned
+    # floor are taken; results stay bit-identical to solo solves.
+    cases = [(513, 385, (w.P5, w.P9, w.P13)[k % 3], 13 + k % 5, 0, 0.9) for k in range(48)]
+    insts = _make(cases, seed=30)
+    for s in (w.P5, w.P9, w.P13):
+        w.wave2d_set_tuning(w.F32C, s, 3 if s == w.P13 else 6, 8)
+    try:
+        b = w.wave2d_batch_create(insts)
+    finally:
+        for s in (w.P5, w.P9, w.P13):
+            w.wave2d_set_tuning(w.F32C, s)
+    try:
+        st = w.wave2d_batch_stats_get(b)
+        assert st["items"] > 0 and st["item_rows"] / st["items"] > 8
+        w.wave2d_batch_run(b)
+        torch.cuda.synchronize()
+    finally:
+        w.wave2d_batch_destroy(b)
+    for t in insts:
+        u, lo, d = _solo(t)
+        assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d)
+
+
 def test_batch_accuracy_against_oracle():
     insts = _make(CASES[:4], seed=10)
     b = w.wave2d_batch_create(insts)
