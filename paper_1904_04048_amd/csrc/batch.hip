@@ -184,7 +184,7 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
     std::vector<Cls> classes;
     for (size_t i = 0; i < b->inst.size(); ++i) {
         const InstRec& rc = b->inst[i];
-        const wave2d_tuning tn = tuning_for(WAVE2D_F32C, rc.p.scheme, rc.p.g.nx, rc.p.g.ny);
+        const wave2d_tuning tn = tuning_for(WAVE2D_F32C, rc.p.scheme, 0, 0);
         auto it = std::find_if(classes.begin(), classes.end(), [&](const Cls& c) {
             return c.kind == rc.p.kind && c.depth == tn.depth && c.rows == tn.rows;
         });
@@ -366,20 +366,33 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
         (void)hipFree(buf);
         return r;
     }
-    // Shapes that fit in registers (deeper 13-point passes spill).
-    const int kmax = (p.kind == KIND13) ? 3 : 6;
-    static const int depths[] = {1, 2, 3, 4, 6};
-    static const int rowsv[] = {8, 16, 24, 32, 48};
+    // Candidate shapes: every supported depth whose interior kernel keeps
+    // its state in registers, with fixed segment heights plus the heights
+    // at which the work items exactly fill k rounds of the resident wave
+    // slots (a last round that is nearly empty leaves the GPU idle).
+    static const int depths[] = {1, 2, 3, 4, 6, 8};
+    static const int rows_fixed[] = {8, 16, 24, 32, 48, 64};
     hipEvent_t e0, e1;
     W2D_HIP(hipEventCreate(&e0));
     W2D_HIP(hipEventCreate(&e1));
     float best_t = 1e30f;
     wave2d_tuning bt{1, 16};
     for (int dep : depths) {
-        if (dep > kmax) continue;
-        for (int rows : rowsv) {
+        const ShapeFit fit = stream_shape_fit(precision, p.kind, dep);
+        if (fit.spills || fit.slots < 1 || fit.strip_cols < 1) continue;
+        const int64_t nstrips = (nx + fit.strip_cols - 1) / fit.strip_cols;
+        std::vector<int> rows_c(std::begin(rows_fixed), std::end(rows_fixed));
+        for (int k = 1; k <= 8; ++k) {
+            const int64_t segs = (int64_t)k * fit.slots / nstrips;
+            if (segs < 1) continue;
+            const int64_t r = (ny + segs - 1) / segs;
+            if (r >= 8 && r <= 256) rows_c.push_back((int)r);
+        }
+        std::sort(rows_c.begin(), rows_c.end());
+        rows_c.erase(std::unique(rows_c.begin(), rows_c.end()), rows_c.end());
+        for (int rows : rows_c) {
+            if (rows > std::max<int64_t>(8, ny)) continue;
             const StreamShape sh{dep, rows, fk};
-            const int reps = std::max(2, 12 / dep);
             auto pass = [&](int k) -> hipError_t {
                 const int a = (k & 1) ? nf : 0, b2 = (k & 1) ? 0 : nf;
                 if (precision == WAVE2D_F64)
@@ -389,13 +402,20 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
                                         (const float*)arr(a + 2), (float*)arr(b2), (float*)arr(b2 + 1),
                                         (float*)arr(b2 + 2), s);
             };
+            // A short probe sizes the timed run to about 2 ms.
+            auto timed = [&](int reps, float* ms) -> int {
+                W2D_HIP(hipEventRecord(e0, s));
+                for (int k = 0; k < reps; ++k) W2D_HIP(pass(k + 1));
+                W2D_HIP(hipEventRecord(e1, s));
+                W2D_HIP(hipEventSynchronize(e1));
+                W2D_HIP(hipEventElapsedTime(ms, e0, e1));
+                return WAVE2D_OK;
+            };
             W2D_HIP(pass(0));
-            W2D_HIP(hipEventRecord(e0, s));
-            for (int k = 0; k < reps; ++k) W2D_HIP(pass(k + 1));
-            W2D_HIP(hipEventRecord(e1, s));
-            W2D_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
-            W2D_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if ((r = timed(2, &ms))) return r;
+            const int reps = std::min(64, std::max(2, (int)std::ceil(2.0f / std::max(ms / 2, 1e-3f))));
+            if ((r = timed(reps, &ms))) return r;
             const float per_level = ms / (reps * dep);
             if (per_level < best_t) {
                 best_t = per_level;
@@ -408,6 +428,7 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
     W2D_HIP(hipStreamSynchronize(s));
     (void)hipFree(buf);
     set_tuning_entry(precision, scheme, bt);
+    set_tuning_size_entry(precision, scheme, nx, ny, bt);
     *best = bt;
     return WAVE2D_OK;
 }

@@ -261,7 +261,7 @@ int run_quantum(wave2d_server* sv)
     std::map<Key, std::vector<Req*>> groups;
     for (Req* r : sv->active) {
         if (r->st != ACTIVE || r->left <= 0) continue;
-        const wave2d_tuning tn = tuning_for(WAVE2D_F32C, r->p.scheme, r->p.g.nx, r->p.g.ny);
+        const wave2d_tuning tn = tuning_for(WAVE2D_F32C, r->p.scheme, 0, 0);
         const int dep = largest_supported((int)std::min<int64_t>(tn.depth, r->left));
         groups[Key{r->p.kind, dep, tn.rows}].push_back(r);
     }

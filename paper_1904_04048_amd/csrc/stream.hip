@@ -20,6 +20,9 @@
 // kernels (point.h), so results are bit-identical to them for every DEPTH,
 // segment length and strip width.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "w2d.h"
 
@@ -848,22 +851,71 @@ bool stream_depth_supported(int depth)
     return depth == 1 || depth == 2 || depth == 3 || depth == 4 || depth == 6 || depth == 8;
 }
 
-int stream_columns_per_wave(int) { return kWave * 2; }
-
 namespace {
 
-// Wave slots of the current device: every CU runs 4 SIMDs, and the
-// streaming kernels fit at least 2 waves per SIMD.
-int wave_slots()
+// Resident waves of a kernel on the current device (all CUs), and whether
+// it uses scratch memory; cached per (kernel, device).
+std::pair<int, bool> kernel_fit(const void* fn)
 {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
-        (void)hipGetLastError();
-        cus = 256;
-    }
-    return cus * 4 * 2;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, std::pair<int, bool>> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({fn, dev});
+    if (it != cache.end()) return it->second;
+    hipFuncAttributes at{};
+    bool spills = false;
+    if (hipFuncGetAttributes(&at, fn) == hipSuccess) spills = at.localSizeBytes > 0;
+    int nb = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWave * kWavesPerBlock, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    (void)hipGetLastError();
+    const std::pair<int, bool> r{nb * kWavesPerBlock * cus, spills};
+    cache[{fn, dev}] = r;
+    return r;
 }
+
+template <class Prec, int K, int DEPTH>
+ShapeFit fit_depth()
+{
+    const auto f = kernel_fit(reinterpret_cast<const void*>(&k_stream_interior<Prec, K, DEPTH, 2>));
+    return ShapeFit{kWave * 2 - 2 * halo_cols<KT<K>::R, DEPTH>(), f.first, f.second};
+}
+
+template <class Prec, int K>
+ShapeFit fit_kind(int depth)
+{
+    switch (depth) {
+    case 1: return fit_depth<Prec, K, 1>();
+    case 2: return fit_depth<Prec, K, 2>();
+    case 3: return fit_depth<Prec, K, 3>();
+    case 4: return fit_depth<Prec, K, 4>();
+    case 6: return fit_depth<Prec, K, 6>();
+    default: return fit_depth<Prec, K, 8>();
+    }
+}
+
+template <class Prec>
+ShapeFit fit_prec(int kind, int depth)
+{
+    switch (kind) {
+    case KIND5: return fit_kind<Prec, KIND5>(depth);
+    case KIND9: return fit_kind<Prec, KIND9>(depth);
+    default: return fit_kind<Prec, KIND13>(depth);
+    }
+}
+
+}  // namespace
+
+ShapeFit stream_shape_fit(int precision, int kind, int depth)
+{
+    if (!stream_depth_supported(depth)) return ShapeFit{0, 0, true};
+    return precision == 0 ? fit_prec<PF64>(kind, depth) : fit_prec<PF32C>(kind, depth);
+}
+
+namespace {
 
 // Segment rows for one batched launch.  A work item recomputes about
 // R*(DEPTH-1) rows of its neighbours per level and streams 2R+1 rows of
@@ -873,12 +925,12 @@ int wave_slots()
 // tuned floor) with the least modelled time wins: tall segments when many
 // instances share the launch, the floor when they are few.
 template <int R, int DEPTH>
-int batch_rows(int rows_min, const std::vector<BatchInst>& insts)
+int batch_rows(int rows_min, const std::vector<BatchInst>& insts, int slots_i)
 {
     constexpr int HP = halo_cols<R, DEPTH>();
     constexpr int SW = kWave * 2 - 2 * HP;
     static const int cand[] = {12, 16, 24, 32, 48, 64};
-    const double slots = wave_slots();
+    const double slots = slots_i;
     auto cost = [&](int r) {
         double items = 0;
         for (const BatchInst& in : insts)
@@ -904,7 +956,8 @@ void tables_depth(int rows, const std::vector<BatchInst>& insts, BatchTables& ge
     using T = typename Prec::T;
     constexpr int CW = 2;
     constexpr int R = KT<K>::R;
-    rows = batch_rows<R, DEPTH>(rows, insts);
+    const int slots = kernel_fit(reinterpret_cast<const void*>(&k_stream_batch<Prec, K, DEPTH, CW, true>)).first;
+    rows = batch_rows<R, DEPTH>(rows, insts, slots);
     gen.rows = inr.rows = rows;
     gen.prefix.assign(1, 0);
     inr.prefix.assign(1, 0);

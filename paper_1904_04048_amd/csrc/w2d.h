@@ -102,7 +102,15 @@ void batch_tables(int precision, int kind, int depth, int rows, const std::vecto
                   BatchTables& inr);
 hipError_t batch_launch(int precision, int kind, int depth, bool interior, const void* d_items, const int* d_prefix,
                         int count, int total, hipStream_t s);
-int stream_columns_per_wave(int precision);
+// How a launch shape fits the current device: output columns per strip,
+// waves of the interior step kernel resident on the whole device, and
+// whether that kernel spills registers to scratch memory.
+struct ShapeFit {
+    int strip_cols;
+    int slots;
+    bool spills;
+};
+ShapeFit stream_shape_fit(int precision, int kind, int depth);
 
 // ---- reductions (norms.hip) -------------------------------------------------
 // Partial sums into `part` (nblk x 4 doubles), then a single-block final
