@@ -88,6 +88,8 @@ def cpu_baseline(p, u0, v0, budget_s=20.0):
 
 COUNTERS_MD = os.path.join(ROOT, "profiles", "k_stream_f32c_9pt_4097_counters.md")
 STATS_MD = os.path.join(ROOT, "profiles", "k_stream_f32c_9pt_4097_kernel_stats.md")
+VALU_MD = os.path.join(ROOT, "profiles", "k_stream_f32c_9pt_4097_valu.md")
+XCDS = 8
 
 
 def kernel_source_hash():
@@ -119,6 +121,14 @@ def summarize(prof_dir):
     kernel scaled by what the same counters read for a plain copy."""
     import csv
     import statistics
+    # The shape the profile runs used, as they printed it (the default height
+    # depends on the device's occupancy, so it is not recomputed here).
+    cfg = None
+    for line in open(os.path.join(prof_dir, "pmc_fetch.log")):
+        if line.startswith("{") and '"profile"' in line:
+            cfg = json.loads(line)["kernel_cfg"]
+    assert cfg is not None, "no profile record in pmc_fetch.log"
+    depth, rows = cfg["depth"], cfg["rows"]
     stats = list(csv.DictReader(open(os.path.join(prof_dir, "prof_bench", "bench_kernel_stats.csv"))))
     lines = ["# Kernel statistics: 9-point compensated-FP32 workload, 4097 x 4097, 2000 levels", "",
              "Command (from the repository root, on one MI355X):", "",
@@ -131,6 +141,25 @@ def summarize(prof_dir):
             name = name[:90] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | {float(r['MinNs'])/1e3:.1f} | "
                      f"{float(r['MaxNs'])/1e3:.1f} | {float(r['Percentage']):.1f} |")
+    # The headline pass kernels alone: the same kernels also run on other
+    # grids (autotuning, batches), so their dispatches are told apart by grid
+    # size; the 4097^2 solve is the grid with the most dispatches.
+    per = {}
+    for r in csv.DictReader(open(os.path.join(prof_dir, "prof_bench", "bench_kernel_trace.csv"))):
+        n = r["Kernel_Name"]
+        for kind in ("interior", "general"):
+            if f"k_stream_{kind}<" in n and f"PF32C, 1, {depth}, 2>" in n:
+                dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                per.setdefault(kind, {}).setdefault(int(r["Grid_Size_X"]), []).append(dur)
+    lines += ["", f"Headline pass kernels (9-point compensated, 4097 x 4097, depth {depth}, rows {rows}):",
+              "", "| kernel | waves | dispatches | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for kind, by_grid in sorted(per.items()):
+        g = max(by_grid, key=lambda k: len(by_grid[k]))
+        v = by_grid[g]
+        lines.append(f"| k_stream_{kind}<PF32C,KIND9,{depth}> | {g // 64} | {len(v)} | {sum(v)/len(v):.1f} | "
+                     f"{min(v):.1f} | {max(v):.1f} |")
+    lines += ["", "The boundary kernel runs on a side stream beside the interior kernel; one pass takes about the "
+              "interior kernel's time.", ""]
     open(STATS_MD, "w").write("\n".join(lines) + "\n")
 
     def per_kernel(path):
@@ -145,11 +174,8 @@ def summarize(prof_dir):
     cw = [v for k, v in write.items() if "copyBuffer" in k][0]
     f_scale = copy_bytes / (statistics.median(cf) * 1024)
     w_scale = copy_bytes / (statistics.median(cw) * 1024)
-    import torch  # noqa: F401  (tuning query loads the library)
-    import paper_1904_04048_amd as w
     from paper_1904_04048_amd import workloads as W
     p = W.c2()
-    depth, rows = w.wave2d_get_tuning(w.F32C, p.scheme, p.nx, p.ny)
     # One pass = the boundary-strip kernel and the interior kernel of this depth.
     tag = f"PF32C, 1, {depth}, 2>"
     kf = [statistics.median(v) for k, v in fetch.items() if "k_stream_" in k and tag in k]
@@ -157,8 +183,7 @@ def summarize(prof_dir):
     assert len(kf) == 2 and len(kw) == 2, (len(kf), len(kw))
     rd = sum(kf) * 1024 * f_scale
     wr = sum(kw) * 1024 * w_scale
-    cfg = {"kernel": KERNEL_NAME, "depth": depth, "rows": rows, "grid": [p.nx, p.ny],
-           "source": kernel_source_hash()}
+    assert cfg["source"] == kernel_source_hash(), "profiles were taken on other kernel sources"
     alg = STATE_BYTES_PER_NODE * p.nx * p.ny
     rec = {"kernel_cfg": cfg, "hbm_bytes_per_launch": int(rd + wr), "read_bytes_per_launch": int(rd),
            "write_bytes_per_launch": int(wr), "algorithmic_bytes_per_launch": alg,
@@ -176,6 +201,55 @@ def summarize(prof_dir):
           f"({(rd + wr)/alg:.2f}x).", "", "```json", json.dumps(rec, indent=1), "```", ""]
     open(COUNTERS_MD, "w").write("\n".join(md))
     print(json.dumps(rec))
+
+    # Instruction issue of the same pass, if the SQ and GRBM counter runs exist.
+    sq_csv = os.path.join(prof_dir, "pmc_sq", "sq_counter_collection.csv")
+    gr_csv = os.path.join(prof_dir, "pmc_grbm", "grbm_counter_collection.csv")
+    if not (os.path.exists(sq_csv) and os.path.exists(gr_csv)):
+        return
+
+    def per_kernel_counter(path):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if "k_stream_" in r["Kernel_Name"] and tag in r["Kernel_Name"]:
+                kind = "interior" if "k_stream_interior" in r["Kernel_Name"] else "boundary"
+                out.setdefault((kind, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: statistics.median(v) for k, v in out.items()}
+    sq = per_kernel_counter(sq_csv)
+    sq.update(per_kernel_counter(gr_csv))
+    simds = 256 * 4
+    lup = p.interior * depth
+    rows_md = []
+    for kind in ("interior", "boundary"):
+        v = {c: sq.get((kind, c)) for c in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_SALU",
+                                            "SQ_INSTS_VMEM_RD", "SQ_WAVES", "GRBM_GUI_ACTIVE")}
+        if any(x is None for x in v.values()):
+            continue
+        cycles = v["GRBM_GUI_ACTIVE"] / XCDS  # the counter sums the 8 XCDs' clocks
+        issue = v["SQ_INSTS_VALU"] * 4 / (simds * cycles)
+        rows_md.append(f"| {kind} | {v['SQ_WAVES']:.0f} | {v['SQ_INSTS_VALU']:.4g} | {v['SQ_INSTS_SALU']:.4g} | "
+                       f"{v['SQ_INSTS_VMEM_RD']:.4g} | {cycles:.0f} | {cycles / 2.4e3:.1f} | {issue:.3f} |")
+    tot_valu = sum(sq.get((k, "SQ_INSTS_VALU"), 0.0) for k in ("interior", "boundary"))
+    md = ["# Vector instruction issue of the dominant kernel pass (compensated FP32, 9-point, 4097 x 4097)", "",
+          "Commands (from the repository root, one MI355X, one counter group per run):", "",
+          "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+          "SQ_WAIT_INST_ANY SQ_INSTS_VMEM_RD SQ_INSTS_SALU --output-format csv -d gpurun_out/pmc_sq -o sq "
+          "-- python3 bench.py --mode profile",
+          "    rocprofv3 --pmc GRBM_GUI_ACTIVE GRBM_COUNT --output-format csv -d gpurun_out/pmc_grbm -o grbm "
+          "-- python3 bench.py --mode profile",
+          "    python3 bench.py --mode summarize", "",
+          f"Shape: depth {depth}, rows {rows}.  Counter runs serialize the two kernels of a pass; medians over "
+          "the dispatches of the profile run.  GRBM_GUI_ACTIVE sums the clocks of the 8 XCDs, so the kernel's "
+          "cycles are that / 8 (us at 2.4 GHz shown beside them).  `issue` = SQ_INSTS_VALU x 4 cycles / "
+          "(1024 SIMDs x cycles): the fraction of SIMD cycles that issue a wave64 vector instruction (one per "
+          "4 cycles per SIMD without packed FP32).  SQ_ACTIVE_INST_VALU reads the same as SQ_INSTS_VALU on "
+          "this device and adds nothing.", "",
+          "| kernel | waves | VALU insts | SALU insts | VMEM reads | cycles | us | issue |",
+          "|---|---|---|---|---|---|---|---|"] + rows_md + ["",
+          f"VALU instructions per grid-point update of the pass (lane operations / useful updates): "
+          f"{tot_valu * 64 / lup:.1f}", ""]
+    open(VALU_MD, "w").write("\n".join(md))
+    print(open(VALU_MD).read())
 
 
 def batch_bench(args):
