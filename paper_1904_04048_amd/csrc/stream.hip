@@ -396,16 +396,46 @@ __device__ __forceinline__ int xcd_block()
 
 // General body: any work item, boundary rule applied everywhere.  `wid`
 // is a wave-uniform boundary work id in [0, nwork).
+// Odd reflection about the boundary lines, continued with period 2(n-1):
+// node x of the extended line maps to the grid node idx it mirrors, and the
+// result is the sign of the image: 1 inside, -1 on a mirror image, 0 on a
+// boundary node.  The boundary rule (boundary nodes 0; the line one outside
+// equal to minus the line one inside) is exactly this extension, and every
+// operation of the update is sign-symmetric (opposite neighbours are paired
+// by commutative additions; rounding to nearest is symmetric), so a level
+// computed from an odd-reflected level is odd-reflected again, with exact
+// zeros on the boundary lines.
+__device__ __forceinline__ int reflect(int x, int n, int& idx)
+{
+    if (x >= 1 && x <= n - 2) {
+        idx = x;
+        return 1;
+    }
+    const int P = 2 * (n - 1);
+    int m = x % P;
+    if (m < 0) m += P;
+    if (m == 0 || m == n - 1) {
+        idx = m;
+        return 0;
+    }
+    if (m < n - 1) {
+        idx = m;
+        return 1;
+    }
+    idx = P - m;
+    return -1;
+}
+
 // One body for every work item.  Interior items (BND false) have a strip
 // inside columns [1, nx-2] and a whole stream (rows y0 - H - NS ..
 // y1 + H + 2 NS) inside rows [2, ny-3]: no boundary rule applies and every
-// access is in bounds without checks.  Boundary items (BND true) apply the
-// rule after every level: rows outside [1, ny-2] are never loaded and are
-// set by the rule (a wave-uniform test per row), and on strips that reach
-// column 0 or nx-1 the columns outside [1, nx-2] are replaced (per-lane
-// selects).  Loads and stores are one vector per field through buffer
-// resources with a scalar row offset.  `wid` is a wave-uniform work id of
-// the item's class.
+// access is in bounds without checks.  Boundary items (BND true) run the
+// same loop on the odd reflection of the grid: rows and columns beyond the
+// boundary are loaded as the negated mirror rows and columns, boundary rows
+// and columns as 0, and from then on the stencil itself keeps the boundary
+// rule at every level (see reflect()).  Loads and stores are one vector per
+// field through buffer resources with a scalar row offset.  `wid` is a
+// wave-uniform work id of the item's class.
 template <class Prec, int K, int DEPTH, int CW, bool BND>
 __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, const Decomp& dc, int wid,
                                             const typename Prec::W& w)
@@ -423,9 +453,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     constexpr bool EXT = (Prec::NW == 1);
     constexpr int E = EXT ? CW + 2 * R : CW;
     constexpr int CB = EXT ? R : 0;  // index of the lane's first column in a row
-    // Column pairs start at even columns, so a pair that is not wholly
-    // inside [0, nx) lies wholly outside [1, nx-2].
-    static_assert(CW == 2, "boundary handling assumes column pairs");
+    static_assert(CW == 2, "reflected loads assume column pairs");
 
     const int lane = threadIdx.x & (kWave - 1);
     int strip, seg;
@@ -441,62 +469,68 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     const int y0 = seg * a.rows;
     const int y1 = min(y0 + a.rows, ny);
     const bool st_lane = (xl >= x0 + HP) && (xl < x0 + HP + SW) && (!BND || xl < nx);
-    // A boundary lane whose pair is not wholly inside [0, nx) loads pair 0
-    // instead (the rule replaces all its values); the last lane of the grid
-    // may store its first column only.
-    const bool lane_in = !BND || (xl >= 0 && xl + CW <= nx);
+    // The last lane of an odd-width grid stores its first column only.
     const bool st_full = !BND || (xl + CW <= nx);
 
-    // Boundary rule along x (strips that reach column 0 or nx-1).
+    // Columns of this lane on the reflected grid.  Adjacent columns mirror
+    // adjacent grid columns, so one vector load at lc covers both (swapped
+    // when the image runs backwards).  Only strips that reach column 0 or
+    // nx-1 have lanes that are not plain.
     const bool edge = BND && (x0 <= 0 || x0 + kWave * CW - 1 >= nx - 1);
-    bool zero_col[CW], ghost[CW];
-    int gsrc_lane[CW], gsrc_m[CW];
-#pragma unroll
-    for (int m = 0; m < CW; ++m) {
-        const int x = xl + m;
-        ghost[m] = (R == 2) && (x == -1 || x == nx);
-        zero_col[m] = !(x >= 1 && x <= nx - 2) && !ghost[m];
-        const int off = ((x == -1) ? 1 : nx - 2) - x0;  // column reflected into a ghost
-        gsrc_lane[m] = off / CW;
-        gsrc_m[m] = off % CW;
+    int lc = xl;
+    bool swp = false, z0 = false, z1 = false, n0 = false, n1 = false;
+    if constexpr (BND) {
+        int i0, i1;
+        const int s0 = reflect(xl, nx, i0), s1 = reflect(xl + 1, nx, i1);
+        swp = i0 > i1;
+        lc = swp ? i1 : i0;
+        z0 = (s0 == 0);
+        z1 = (s1 == 0);
+        n0 = (s0 < 0);
+        n1 = (s1 < 0);
     }
-    auto fix_columns = [&](T (&v)[NW][E]) {
-#pragma unroll
-        for (int f = 0; f < NW; ++f) {
-            T g[CW];
-#pragma unroll
-            for (int m = 0; m < CW; ++m) g[m] = T(0);
-            if constexpr (R == 2) {
-#pragma unroll
-                for (int mm = 0; mm < CW; ++mm) {
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) {
-                        const T s = __shfl(v[f][CB + mm], gsrc_lane[m]);
-                        if (gsrc_m[m] == mm) g[m] = -s;
-                    }
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < CW; ++m) {
-                if (zero_col[m]) v[f][CB + m] = T(0);
-                if (ghost[m]) v[f][CB + m] = g[m];
-            }
+    // Loaded values of one row (two columns) as the reflected grid holds
+    // them; sy is the row's sign.  Applied where the row is first used, not
+    // right after its load, so the load keeps its latency hidden.
+    auto reflect_vals = [&](T& v0, T& v1, int sy) {
+        if (sy == 0) {
+            v0 = v1 = T(0);
+            return;
         }
-    };
-    auto neg_copy = [&](T (&dst)[NW][E], const T (&src)[NW][E]) {
-#pragma unroll
-        for (int f = 0; f < NW; ++f)
-#pragma unroll
-            for (int e = 0; e < E; ++e) dst[f][e] = -src[f][e];
+        if (edge) {
+            const T e0 = swp ? v1 : v0, e1 = swp ? v0 : v1;
+            v0 = z0 ? T(0) : (n0 ? -e0 : e0);
+            v1 = z1 ? T(0) : (n1 ? -e1 : e1);
+        }
+        if (sy < 0) {
+            v0 = -v0;
+            v1 = -v1;
+        }
     };
 
     const int jA = floor_div(y0 - H, NS) * NS;
     const int jhi = y1 - 1 + H;
-    // Rows this wave touches: loads from jA - R, stores up to y1 - 1, loads
-    // up to the last iteration's next row (< jhi + NS + 1); boundary items
-    // touch rows inside [0, ny) only.  The host bounds the byte size.
-    const int base_row = BND ? max(jA - NS, 0) : jA - NS;
-    const int top_row = BND ? min(jhi + 2 * NS + 1, ny) : jhi + 2 * NS + 1;
+    // Rows this wave touches: loads from jA - R up to the last iteration's
+    // next row (< jhi + NS + 1), stores in [y0, y1).  Boundary items read the
+    // mirror images of rows outside the grid.  The host bounds the byte size.
+    int base_row = jA - NS, top_row = jhi + 2 * NS + 1;
+    if constexpr (BND) {
+        const int ra = jA - R, rb = jhi + NS;
+        const int P = 2 * (ny - 1);
+        if (ra >= 0 && rb <= ny - 1) {
+            base_row = ra;
+            top_row = rb + 1;
+        } else if (rb - ra + 1 < P && ra < 0 && rb <= ny - 1 && -ra <= ny - 1) {
+            base_row = 0;
+            top_row = max(rb, -ra) + 1;
+        } else if (rb - ra + 1 < P && ra >= 0 && rb > ny - 1 && P - rb >= 0) {
+            base_row = min(ra, P - rb);
+            top_row = ny;
+        } else {
+            base_row = 0;
+            top_row = ny;
+        }
+    }
     const uint32_t rbytes = (uint32_t)(top_row - base_row) * (uint32_t)ld * (uint32_t)sizeof(T);
     __amdgpu_buffer_rsrc_t rs_in[2], rs_out[2];
     rs_in[0] = make_rsrc(a.in_w0 + (size_t)base_row * ld, rbytes);
@@ -505,7 +539,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     rs_out[1] = make_rsrc((NW > 1 ? a.out_w1 : a.out_w0) + (size_t)base_row * ld, rbytes);
     const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.in_p + (size_t)base_row * ld, rbytes);
     const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc((a.out_p ? a.out_p : a.out_w0) + (size_t)base_row * ld, rbytes);
-    const uint32_t voff = (uint32_t)((lane_in ? xl : 0) * (int)sizeof(T));
+    const uint32_t voff = (uint32_t)(lc * (int)sizeof(T));
     const uint32_t voff_st = (uint32_t)(xl * (int)sizeof(T));
     const int row_bytes = ld * (int)sizeof(T);
 
@@ -523,36 +557,30 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
             for (int m = 0; m < CW; ++m) pf[t][s][m] = T(0);
         }
 
-    // Level-0 row jj (window fields) and the point field at row jj - R.
-    // Boundary rows (and rows outside the grid) are not loaded but set to 0.
-    // With DEPTH 1 the point field is read only on this segment's rows and
-    // output columns (it may be the array being written in place).
-    auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
-        if (!BND || (jj >= 1 && jj <= ny - 2)) {
-            const uint32_t so = (uint32_t)((jj - base_row) * row_bytes);
-#pragma unroll
-            for (int f = 0; f < NW; ++f) {
-                const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
-#pragma unroll
-                for (int m = 0; m < CW; ++m) v[f][CB + m] = x.v[m];
-            }
-        } else {
-#pragma unroll
-            for (int f = 0; f < NW; ++f)
-#pragma unroll
-                for (int m = 0; m < CW; ++m) v[f][CB + m] = T(0);
-        }
+    // Point-field row read with window row jj.  With DEPTH 1 it is read only
+    // on this segment's rows and output columns (it may be the array being
+    // written in place).
+    auto point_row = [&](int jj) {
         int jp = jj - R;
-        if constexpr (DEPTH == 1) {
-            jp = min(max(jp, y0), y1 - 1);
-            if (!st_lane) return;
-        } else if constexpr (BND) {
-            if (jp < 1 || jp > ny - 2) {
+        if constexpr (DEPTH == 1) jp = min(max(jp, y0), y1 - 1);
+        return jp;
+    };
+    // Level-0 row jj (window fields) and the point field at point_row(jj).
+    auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
+        int jr = jj;
+        if constexpr (BND) (void)reflect(jj, ny, jr);
+        const uint32_t so = (uint32_t)((jr - base_row) * row_bytes);
 #pragma unroll
-                for (int m = 0; m < CW; ++m) p[m] = T(0);
-                return;
-            }
+        for (int f = 0; f < NW; ++f) {
+            const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) v[f][CB + m] = x.v[m];
         }
+        int jp = point_row(jj);
+        if constexpr (DEPTH == 1) {
+            if (!st_lane) return;
+        }
+        if constexpr (BND) (void)reflect(jp, ny, jp);
         const Vec<T, CW> x = buf_load<T, CW>(rs_pin, voff, (uint32_t)((jp - base_row) * row_bytes));
 #pragma unroll
         for (int m = 0; m < CW; ++m) p[m] = x.v[m];
@@ -560,8 +588,8 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
 
     // Differences carried down the rows of each level (single precision).
     // They are refreshed at every row of every level, also where a level's
-    // update is skipped (warm-up, boundary rows), so the first updated row
-    // of a level finds the previous row's values.
+    // update is skipped during the warm-up, so the first updated row of a
+    // level finds the previous row's values.
     Carry<CW> carry[EXT ? 1 : DEPTH];
     if constexpr (!EXT) {
 #pragma unroll
@@ -572,15 +600,17 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     }
 
     auto phase = [&](int ph, int j, bool warm) {
-        // Finish level-0 row j (its loads went out one row ago).
+        // Finish level-0 row j and its point-field row (loaded one row ago).
         if constexpr (BND) {
-            if (edge && j >= 1 && j <= ny - 2) fix_columns(win[0][ph]);
+            int jr;
+            const int sy = reflect(j, ny, jr);
+#pragma unroll
+            for (int f = 0; f < NW; ++f) reflect_vals(win[0][ph][f][CB], win[0][ph][f][CB + 1], sy);
+            const int sp = reflect(point_row(j), ny, jr);
+            T(&p)[CW] = pf[0][mod_c(ph - R, NS)];
+            reflect_vals(p[0], p[1], sp);
         }
         if constexpr (EXT) extend_row<T, NW, CW, R>(win[0][ph]);
-        if constexpr (BND && R == 2) {
-            if (j == 1) neg_copy(win[0][mod_c(ph - 2, NS)], win[0][ph]);
-            if (j == ny) neg_copy(win[0][ph], win[0][mod_c(ph - 2, NS)]);
-        }
         // Levels 1..DEPTH at rows j - t*R; the next row's loads go out right
         // after level 1, whose inputs they overwrite.
 #pragma unroll
@@ -588,38 +618,20 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
             if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
             const int y = j - t * R;
             const bool skip = warm && y < y0 - (DEPTH - t) * R;
-            const bool inside = !BND || (y >= 1 && y <= ny - 2);
             const int sy = mod_c(ph - t * R, NS);
             T nv[NW][E];
             T np[CW];
             if constexpr (EXT) {
                 if (skip) continue;
-                if (inside)
-                    row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
-                                            win[t - 1][mod_c(ph - t * R - 1, NS)],
-                                            win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                            win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
+                row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
             } else {
                 row_update_carry<K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
                                         win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], carry[t - 1], w,
-                                        !skip && inside, nv, np);
+                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], carry[t - 1], w, !skip,
+                                        nv, np);
                 if (skip) continue;
-            }
-            if constexpr (BND) {
-                if (!inside) {
-#pragma unroll
-                    for (int f = 0; f < NW; ++f)
-#pragma unroll
-                        for (int m = 0; m < CW; ++m) nv[f][CB + m] = T(0);
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) np[m] = T(0);
-                } else if (edge) {
-                    fix_columns(nv);
-#pragma unroll
-                    for (int m = 0; m < CW; ++m)
-                        if (zero_col[m] || ghost[m]) np[m] = T(0);
-                }
             }
             if (t < DEPTH) {
                 if constexpr (EXT) extend_row<T, NW, CW, R>(nv);
@@ -630,10 +642,6 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
                     for (int e = 0; e < E; ++e) dst[f][e] = nv[f][e];
 #pragma unroll
                 for (int m = 0; m < CW; ++m) pf[t][sy][m] = np[m];
-                if constexpr (BND && R == 2) {
-                    if (y == 1) neg_copy(win[t][mod_c(ph - t * R - 2, NS)], dst);
-                    if (y == ny) neg_copy(dst, win[t][mod_c(ph - t * R - 2, NS)]);
-                }
             } else if (y >= y0 && y < y1 && st_lane) {
                 const uint32_t so = (uint32_t)((y - base_row) * row_bytes);
                 if (st_full) {
