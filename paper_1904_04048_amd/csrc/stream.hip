@@ -508,14 +508,20 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
         }
     };
 
+    // Rows are fetched PF rows ahead of the phase that first uses them: with
+    // DEPTH > 1 a row's loads land in a staging ring (indexed like the
+    // window, by row mod NS) and are moved into the window one phase before
+    // use, so each load has about two phases of work to hide behind.
+    constexpr int PF = (DEPTH > 1) ? 3 : 1;
     const int jA = floor_div(y0 - H, NS) * NS;
     const int jhi = y1 - 1 + H;
-    // Rows this wave touches: loads from jA - R up to the last iteration's
-    // next row (< jhi + NS + 1), stores in [y0, y1).  Boundary items read the
-    // mirror images of rows outside the grid.  The host bounds the byte size.
+    // Rows this wave touches: loads from jA - R up to PF rows past the last
+    // iteration (< jhi + NS + PF), stores in [y0, y1).  Boundary items read
+    // the mirror images of rows outside the grid.  The host bounds the byte
+    // size.
     int base_row = jA - NS, top_row = jhi + 2 * NS + 1;
     if constexpr (BND) {
-        const int ra = jA - R, rb = jhi + NS;
+        const int ra = jA - R, rb = jhi + NS + PF - 1;
         const int P = 2 * (ny - 1);
         if (ra >= 0 && rb <= ny - 1) {
             base_row = ra;
@@ -565,16 +571,19 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
         if constexpr (DEPTH == 1) jp = min(max(jp, y0), y1 - 1);
         return jp;
     };
+    T stg[PF > 1 ? NS : 1][NW][CW];
+    T stp[PF > 1 ? NS : 1][CW];
     // Level-0 row jj (window fields) and the point field at point_row(jj).
-    auto issue_loads = [&](int jj, T (&v)[NW][E], T (&p)[CW]) {
+    auto issue_loads = [&](int jj, auto& v, auto& p) {
         int jr = jj;
         if constexpr (BND) (void)reflect(jj, ny, jr);
         const uint32_t so = (uint32_t)((jr - base_row) * row_bytes);
+        constexpr int off = (sizeof(v[0]) / sizeof(T) == E) ? CB : 0;  // window rows carry the extension
 #pragma unroll
         for (int f = 0; f < NW; ++f) {
             const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
 #pragma unroll
-            for (int m = 0; m < CW; ++m) v[f][CB + m] = x.v[m];
+            for (int m = 0; m < CW; ++m) v[f][off + m] = x.v[m];
         }
         int jp = point_row(jj);
         if constexpr (DEPTH == 1) {
@@ -611,11 +620,25 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
             reflect_vals(p[0], p[1], sp);
         }
         if constexpr (EXT) extend_row<T, NW, CW, R>(win[0][ph]);
-        // Levels 1..DEPTH at rows j - t*R; the next row's loads go out right
-        // after level 1, whose inputs they overwrite.
+        // Levels 1..DEPTH at rows j - t*R; the next row enters the window
+        // right after level 1, whose inputs it overwrites.
 #pragma unroll
         for (int t = 1; t <= DEPTH; ++t) {
-            if (t == 2) issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
+            if (t == 2) {
+                if constexpr (PF > 1) {
+                    T(&dv)[NW][E] = win[0][mod_c(ph + 1, NS)];
+                    T(&dp)[CW] = pf[0][mod_c(ph + 1 - R, NS)];
+#pragma unroll
+                    for (int f = 0; f < NW; ++f)
+#pragma unroll
+                        for (int m = 0; m < CW; ++m) dv[f][CB + m] = stg[mod_c(ph + 1, NS)][f][m];
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) dp[m] = stp[mod_c(ph + 1, NS)][m];
+                    issue_loads(j + PF, stg[mod_c(ph + PF, NS)], stp[mod_c(ph + PF, NS)]);
+                } else {
+                    issue_loads(j + 1, win[0][mod_c(ph + 1, NS)], pf[0][mod_c(ph + 1 - R, NS)]);
+                }
+            }
             const int y = j - t * R;
             const bool skip = warm && y < y0 - (DEPTH - t) * R;
             const int sy = mod_c(ph - t * R, NS);
@@ -670,6 +693,10 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     };
 
     issue_loads(jA, win[0][0], pf[0][mod_c(-R, NS)]);
+    if constexpr (PF > 1) {
+#pragma unroll
+        for (int k = 1; k < PF; ++k) issue_loads(jA + k, stg[mod_c(k, NS)], stp[mod_c(k, NS)]);
+    }
     int jb = jA;
     // Warm-up: levels whose rows are not yet needed are skipped.
     for (; jb <= jhi && jb < y0 + H; jb += NS) {
