@@ -231,7 +231,7 @@ int fill_rows(int precision, int kind, int depth, int64_t nx, int64_t ny)
 wave2d_tuning default_tuning(int precision, int scheme, int64_t nx, int64_t ny)
 {
     int depth;
-    if (precision == WAVE2D_F32C) depth = (scheme == WAVE2D_P13) ? 3 : (scheme == WAVE2D_P5) ? 8 : 6;
+    if (precision == WAVE2D_F32C) depth = (scheme == WAVE2D_P13) ? 4 : (scheme == WAVE2D_P5) ? 8 : 6;
     else depth = (scheme == WAVE2D_P13) ? 3 : 6;
     const int rows = (nx > 0 && ny > 0) ? fill_rows(precision, kind_of(scheme), depth, nx, ny) : 8;
     return wave2d_tuning{depth, rows};
