@@ -143,6 +143,41 @@ def test_stream_f32c_bitwise_equals_simple(scheme, depth, rows):
         assert torch.equal(a, b)
 
 
+NARROW = [(3, 3), (4, 5), (5, 40), (40, 5), (9, 130), (130, 9), (127, 3), (3, 127), (129, 131)]
+
+
+@pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
+@pytest.mark.parametrize("depth", [2, 4, 6, 8])
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_stream_bitwise_on_narrow_grids(scheme, depth, prec):
+    # Grids narrower than a strip's halo: boundary items read the odd
+    # reflection of the grid folded several times.
+    for (nx, ny) in NARROW:
+        u0, v0 = rough_data(nx, ny, nx * 1000 + ny)
+        h = 1.0 / (max(nx, ny) - 1)
+        tau = _lam(scheme) * h
+        U0, V0 = dev_grid(u0), dev_grid(v0)
+        for rows in (8, 13):
+            outs = []
+            for simple in (True, False):
+                if prec == "f64":
+                    if not simple:
+                        w.wave2d_set_tuning(w.F64, scheme, depth, rows)
+                    UP, UC = torch.empty_like(U0), torch.empty_like(U0)
+                    w.wave2d_run(U0, V0, UP, UC, h, tau, 1.0, scheme, 2 * depth + 3, w.KERNEL_SIMPLE if simple else 0)
+                    outs.append((UP.clone(), UC.clone()))
+                else:
+                    if not simple:
+                        w.wave2d_set_tuning(w.F32C, scheme, depth, rows)
+                    u = torch.empty(U0.shape, dtype=torch.float32, device=U0.device)
+                    lo, d = torch.empty_like(u), torch.empty_like(u)
+                    w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, scheme, 2 * depth + 3,
+                                      w.KERNEL_SIMPLE if simple else 0)
+                    outs.append((u.clone(), lo.clone(), d.clone()))
+            for a, b in zip(outs[0], outs[1]):
+                assert torch.equal(a, b), (nx, ny, rows)
+
+
 def test_step_is_resumable_and_bitwise():
     """run(K) equals run(K1) followed by step(K - K1), bit for bit; and a
     second identical run gives identical bits (deterministic)."""
