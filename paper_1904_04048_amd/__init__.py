@@ -16,11 +16,11 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13,
+from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13, PERIODIC,
                    BatchStats, Instance, Request, Result, ServerStats, Tuning, Wave2dError)
 
 __all__ = [
-    "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE",
+    "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE", "PERIODIC",
     "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_work_bytes", "wave2d_first_step",
     "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",

@@ -11,6 +11,7 @@ OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5
 P5, P9, P13, C9 = 5, 9, 13, 109
 FIRST_CONVENTIONAL = 0x1
 ALLOW_UNSTABLE = 0x2
+PERIODIC = 0x4
 KERNEL_SIMPLE = 0x100
 F64, F32C = 0, 1
 

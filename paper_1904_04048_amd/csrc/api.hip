@@ -125,7 +125,7 @@ int check_finite_pos(double v, const char* name)
 int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c, int scheme, uint32_t flags,
              Params* p)
 {
-    const uint32_t known = WAVE2D_FIRST_CONVENTIONAL | WAVE2D_ALLOW_UNSTABLE | WAVE2D_KERNEL_SIMPLE;
+    const uint32_t known = WAVE2D_FIRST_CONVENTIONAL | WAVE2D_ALLOW_UNSTABLE | WAVE2D_KERNEL_SIMPLE | WAVE2D_PERIODIC;
     if (flags & ~known) return fail(WAVE2D_EINVAL, "unknown flag bits 0x%x", flags & ~known);
     if (nx < 3 || ny < 3) return fail(WAVE2D_EINVAL, "grid must have at least 3 x 3 nodes (got %lld x %lld)",
                                       (long long)nx, (long long)ny);
@@ -141,7 +141,13 @@ int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c,
     p->scheme = scheme;
     p->kind = kind_of(scheme);
     if (p->kind < 0) return fail(WAVE2D_EINVAL, "unknown scheme %d", scheme);
-    p->g = Grid{(int)nx, (int)ny, (int)ld};
+    p->g = Grid{(int)nx, (int)ny, (int)ld, (flags & WAVE2D_PERIODIC) ? 1 : 0};
+    if (p->g.periodic) {
+        const int rr = (p->kind == KIND13) ? 2 : 1;
+        if (nx < 2 * rr + 1 || ny < 2 * rr + 1)
+            return fail(WAVE2D_EINVAL, "periodic grids need at least %d x %d nodes for scheme %d", 2 * rr + 1,
+                        2 * rr + 1, scheme);
+    }
     p->lam = c * tau / h;
     const double lmax = lambda_max_of(scheme);
     if (!(flags & WAVE2D_ALLOW_UNSTABLE) && p->lam > lmax * (1.0 + 1e-12))
@@ -149,6 +155,15 @@ int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c,
                     p->lam, lmax, scheme);
     node_weights(scheme, p->lam, p->wa, p->wb, &p->has_b);
     return WAVE2D_OK;
+}
+
+// Periodic grids run the temporally blocked kernels only when no lane's
+// column pair straddles the wrap (even nx) and the whole grid fits one
+// buffer range; other periodic grids use the one-node-per-thread kernels.
+bool stream_ok(const Grid& g, size_t elt)
+{
+    if (!g.periodic) return true;
+    return (g.nx % 2 == 0) && (uint64_t)g.ld * (uint64_t)g.ny * elt < (uint64_t(1) << 31);
 }
 
 StepW64 step_w64(const Params& p) { return StepW64{2.0 * p.wa[0], 2.0 * p.wa[1], 2.0 * p.wa[2]}; }
@@ -403,7 +418,7 @@ int run_steps_f64(const Params& p, uint32_t flags, int64_t steps, double* up, do
     const StepW64 w = step_w64(p);
     const Grid& g = p.g;
     const wave2d_tuning tn = tuning_for(WAVE2D_F64, p.scheme, g.nx, g.ny);
-    const bool simple = flags & WAVE2D_KERNEL_SIMPLE;
+    const bool simple = (flags & WAVE2D_KERNEL_SIMPLE) || !stream_ok(g, sizeof(double));
     if (simple || tn.depth == 1 || steps == 1) {
         // In place: level k+1 overwrites level k-1, then the roles swap.
         double* a = up;
@@ -457,7 +472,7 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
     float* wu = (float*)base;
     float* wl = (float*)(base + stride);
     float* wd = (float*)(base + 2 * stride);
-    const bool simple = flags & WAVE2D_KERNEL_SIMPLE;
+    const bool simple = (flags & WAVE2D_KERNEL_SIMPLE) || !stream_ok(g, sizeof(float));
     const Fork* fk = nullptr;
     if (!simple && (r = side_of(s, &fk))) return r;
     const wave2d_tuning tn = tuning_for(WAVE2D_F32C, p.scheme, g.nx, g.ny);

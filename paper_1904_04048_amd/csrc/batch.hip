@@ -136,6 +136,11 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
             delete b;
             return fail(WAVE2D_EINVAL, "instance %lld: steps must be >= 1", (long long)i);
         }
+        if (!stream_ok(rec.p.g, sizeof(float))) {
+            delete b;
+            return fail(WAVE2D_EINVAL, "instance %lld: periodic batch instances need an even nx and ld*ny*4 < 2^31",
+                        (long long)i);
+        }
         if ((r = check_ptrs(rec.p.g, {{in.u0, 8}, {in.v0, 8}, {in.u, 4}, {in.lo, 4}, {in.d, 4}}))) {
             delete b;
             return fail(r, "instance %lld: %s", (long long)i, wave2d_last_error());

@@ -41,6 +41,7 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb);
 size_t grid_bytes(const Grid& g, size_t elt);
 int check_ptrs(const Grid& g, std::initializer_list<std::pair<const void*, size_t>> arrs);
 wave2d_tuning tuning_for(int precision, int scheme, int64_t nx, int64_t ny);
+bool stream_ok(const Grid& g, size_t elt);
 void set_tuning_entry(int precision, int scheme, const wave2d_tuning& t);
 void set_tuning_size_entry(int precision, int scheme, int64_t nx, int64_t ny, const wave2d_tuning& t);
 int get_device(int* dev);

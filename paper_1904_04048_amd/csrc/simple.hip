@@ -4,7 +4,8 @@
 //
 // Every grid read goes through bc_load, which applies the boundary rule:
 // boundary nodes read as 0, a node one line outside reads as minus its
-// mirror image (only the 13-point stencil reaches there).
+// mirror image (only the 13-point stencil reaches there); on periodic grids
+// indices wrap around and every node is updated.
 #include "w2d.h"
 
 namespace w2d {
@@ -13,8 +14,14 @@ namespace {
 constexpr int BX = 64, BY = 4;
 
 template <typename T>
-__device__ __forceinline__ T bc_load(const T* __restrict__ p, int nx, int ny, int ld, int i, int j)
+__device__ __forceinline__ T bc_load(const T* __restrict__ p, const Grid& g, int i, int j)
 {
+    const int nx = g.nx, ny = g.ny, ld = g.ld;
+    if (g.periodic) {
+        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
+        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
+        return p[(size_t)j * ld + i];
+    }
     bool neg = false;
     if (i < 0) { i = -i; neg = !neg; }
     else if (i > nx - 1) { i = 2 * (nx - 1) - i; neg = !neg; }
@@ -26,36 +33,38 @@ __device__ __forceinline__ T bc_load(const T* __restrict__ p, int nx, int ny, in
 }
 
 template <int K, typename T>
-__device__ __forceinline__ Nbh<T> gather(const T* __restrict__ p, int nx, int ny, int ld, int i, int j)
+__device__ __forceinline__ Nbh<T> gather(const T* __restrict__ p, const Grid& g, int i, int j)
 {
     Nbh<T> v;
-    v.C = bc_load(p, nx, ny, ld, i, j);
-    v.E = bc_load(p, nx, ny, ld, i + 1, j);
-    v.W = bc_load(p, nx, ny, ld, i - 1, j);
-    v.N = bc_load(p, nx, ny, ld, i, j + 1);
-    v.S = bc_load(p, nx, ny, ld, i, j - 1);
+    v.C = bc_load(p, g, i, j);
+    v.E = bc_load(p, g, i + 1, j);
+    v.W = bc_load(p, g, i - 1, j);
+    v.N = bc_load(p, g, i, j + 1);
+    v.S = bc_load(p, g, i, j - 1);
     if constexpr (KT<K>::DIAG) {
-        v.NE = bc_load(p, nx, ny, ld, i + 1, j + 1);
-        v.NW = bc_load(p, nx, ny, ld, i - 1, j + 1);
-        v.SE = bc_load(p, nx, ny, ld, i + 1, j - 1);
-        v.SW = bc_load(p, nx, ny, ld, i - 1, j - 1);
+        v.NE = bc_load(p, g, i + 1, j + 1);
+        v.NW = bc_load(p, g, i - 1, j + 1);
+        v.SE = bc_load(p, g, i + 1, j - 1);
+        v.SW = bc_load(p, g, i - 1, j - 1);
     } else {
         v.NE = v.NW = v.SE = v.SW = T(0);
     }
     if constexpr (KT<K>::AX2) {
-        v.EE = bc_load(p, nx, ny, ld, i + 2, j);
-        v.WW = bc_load(p, nx, ny, ld, i - 2, j);
-        v.NN = bc_load(p, nx, ny, ld, i, j + 2);
-        v.SS = bc_load(p, nx, ny, ld, i, j - 2);
+        v.EE = bc_load(p, g, i + 2, j);
+        v.WW = bc_load(p, g, i - 2, j);
+        v.NN = bc_load(p, g, i, j + 2);
+        v.SS = bc_load(p, g, i, j - 2);
     } else {
         v.EE = v.WW = v.NN = v.SS = T(0);
     }
     return v;
 }
 
-__device__ __forceinline__ bool interior(int nx, int ny, int i, int j)
+// Nodes the update writes: every node on a periodic grid, else the
+// non-boundary nodes.
+__device__ __forceinline__ bool interior(const Grid& g, int i, int j)
 {
-    return i > 0 && i < nx - 1 && j > 0 && j < ny - 1;
+    return g.periodic || (i > 0 && i < g.nx - 1 && j > 0 && j < g.ny - 1);
 }
 
 template <int K>
@@ -65,9 +74,9 @@ __global__ __launch_bounds__(BX* BY) void k_first_step(Grid g, FirstW w, const d
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     double r = 0.0;
-    if (interior(g.nx, g.ny, i, j)) {
-        const Nbh<double> a = gather<K>(u0, g.nx, g.ny, g.ld, i, j);
-        const Nbh<double> b = gather<K>(v0, g.nx, g.ny, g.ld, i, j);
+    if (interior(g, i, j)) {
+        const Nbh<double> a = gather<K>(u0, g, i, j);
+        const Nbh<double> b = gather<K>(v0, g, i, j);
         const double sa = lap_diff<K>(a, w.a10, w.a11, w.a20);
         const double sb = w.poisson ? lap_diff<K>(b, w.b10, w.b11, w.b20) : 0.0;
         r = first_update(a.C, sa, b.C, sb, w.tau);
@@ -83,9 +92,9 @@ __global__ __launch_bounds__(BX* BY) void k_first_step_f32c(Grid g, FirstW w, co
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     float ru = 0.f, rl = 0.f, rd = 0.f;
-    if (interior(g.nx, g.ny, i, j)) {
-        const Nbh<double> a = gather<K>(u0, g.nx, g.ny, g.ld, i, j);
-        const Nbh<double> b = gather<K>(v0, g.nx, g.ny, g.ld, i, j);
+    if (interior(g, i, j)) {
+        const Nbh<double> a = gather<K>(u0, g, i, j);
+        const Nbh<double> b = gather<K>(v0, g, i, j);
         const double sa = lap_diff<K>(a, w.a10, w.a11, w.a20);
         const double sb = w.poisson ? lap_diff<K>(b, w.b10, w.b11, w.b20) : 0.0;
         f32c_split(first_update(a.C, sa, b.C, sb, w.tau), a.C, ru, rl, rd);
@@ -103,8 +112,8 @@ __global__ __launch_bounds__(BX* BY) void k_step_f64(Grid g, StepW64 w, const do
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     double r = 0.0;
-    if (interior(g.nx, g.ny, i, j)) {
-        const Nbh<double> v = gather<K>(u_cur, g.nx, g.ny, g.ld, i, j);
+    if (interior(g, i, j)) {
+        const Nbh<double> v = gather<K>(u_cur, g, i, j);
         r = f64_update(v.C, u_prev[(size_t)j * g.ld + i], lap_diff<K>(v, w.w10, w.w11, w.w20));
     }
     u_next[(size_t)j * g.ld + i] = r;
@@ -120,9 +129,9 @@ __global__ __launch_bounds__(BX* BY) void k_step_f32c(Grid g, StepW32 w, const f
     if (i >= g.nx || j >= g.ny) return;
     float ru = 0.f, rl = 0.f, rd = 0.f;
     const size_t o = (size_t)j * g.ld + i;
-    if (interior(g.nx, g.ny, i, j)) {
-        const Nbh<float> a = gather<K>(u, g.nx, g.ny, g.ld, i, j);
-        const Nbh<float> b = gather<K>(lo, g.nx, g.ny, g.ld, i, j);
+    if (interior(g, i, j)) {
+        const Nbh<float> a = gather<K>(u, g, i, j);
+        const Nbh<float> b = gather<K>(lo, g, i, j);
         const float su = lap_diff<K>(a, w.w10, w.w11, w.w20);
         const float sl = lap_sum<K>(b, w.wc, w.w10, w.w11, w.w20);
         f32c_update(su, sl, a.C, b.C, d[o], ru, rl, rd);
@@ -139,8 +148,8 @@ __global__ __launch_bounds__(BX* BY) void k_init(Grid g, const double* __restric
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const size_t o = (size_t)j * g.ld + i;
-    float ru = 0.f, rl = 0.f, rd = 0.f;
-    if (interior(g.nx, g.ny, i, j)) f32c_split(c[o], p[o], ru, rl, rd);
+    float ru, rl, rd;
+    f32c_split(c[o], p[o], ru, rl, rd);
     u[o] = ru;
     lo[o] = rl;
     d[o] = rd;
@@ -152,7 +161,7 @@ __global__ __launch_bounds__(BX* BY) void k_export(Grid g, const float* __restri
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const size_t o = (size_t)j * g.ld + i;
-    out[o] = interior(g.nx, g.ny, i, j) ? f32c_join(u[o], lo[o]) : 0.0;
+    out[o] = f32c_join(u[o], lo[o]);
 }
 
 __global__ __launch_bounds__(BX* BY) void k_copy3(Grid g, const float* a, const float* b, const float* c, float* a2,
@@ -181,7 +190,7 @@ __global__ __launch_bounds__(BX* BY) void k_copy_interior(Grid g, const double* 
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     const size_t o = (size_t)j * g.ld + i;
-    b[o] = interior(g.nx, g.ny, i, j) ? a[o] : 0.0;
+    b[o] = interior(g, i, j) ? a[o] : 0.0;
 }
 
 __global__ __launch_bounds__(BX* BY) void k_swap(Grid g, double* a, double* b)

@@ -426,6 +426,17 @@ __device__ __forceinline__ int reflect(int x, int n, int& idx)
     return -1;
 }
 
+// Grid node that node x of the extended line stands for, and its sign: the
+// odd reflection above, or on periodic grids plain wrapping (sign 1).
+__device__ __forceinline__ int map_node(int x, int n, bool periodic, int& idx)
+{
+    if (!periodic) return reflect(x, n, idx);
+    int m = x % n;
+    if (m < 0) m += n;
+    idx = m;
+    return 1;
+}
+
 // One body for every work item.  Interior items (BND false) have a strip
 // inside columns [1, nx-2] and a whole stream (rows y0 - H - NS ..
 // y1 + H + 2 NS) inside rows [2, ny-3]: no boundary rule applies and every
@@ -433,7 +444,10 @@ __device__ __forceinline__ int reflect(int x, int n, int& idx)
 // same loop on the odd reflection of the grid: rows and columns beyond the
 // boundary are loaded as the negated mirror rows and columns, boundary rows
 // and columns as 0, and from then on the stencil itself keeps the boundary
-// rule at every level (see reflect()).  Loads and stores are one vector per
+// rule at every level (see reflect()).  On periodic grids they load the
+// wrapped rows and columns instead (the host runs this path only for even
+// nx, so a lane's column pair never straddles the wrap).  Interior items
+// never reach the grid's edges and serve both rules.  Loads and stores are one vector per
 // field through buffer resources with a scalar row offset.  `wid` is a
 // wave-uniform work id of the item's class.
 template <class Prec, int K, int DEPTH, int CW, bool BND>
@@ -476,12 +490,13 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     // adjacent grid columns, so one vector load at lc covers both (swapped
     // when the image runs backwards).  Only strips that reach column 0 or
     // nx-1 have lanes that are not plain.
-    const bool edge = BND && (x0 <= 0 || x0 + kWave * CW - 1 >= nx - 1);
+    const bool per = a.g.periodic != 0;
+    const bool edge = BND && !per && (x0 <= 0 || x0 + kWave * CW - 1 >= nx - 1);
     int lc = xl;
     bool swp = false, z0 = false, z1 = false, n0 = false, n1 = false;
     if constexpr (BND) {
         int i0, i1;
-        const int s0 = reflect(xl, nx, i0), s1 = reflect(xl + 1, nx, i1);
+        const int s0 = map_node(xl, nx, per, i0), s1 = map_node(xl + 1, nx, per, i1);
         swp = i0 > i1;
         lc = swp ? i1 : i0;
         z0 = (s0 == 0);
@@ -523,7 +538,12 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     if constexpr (BND) {
         const int ra = jA - R, rb = jhi + NS + PF - 1;
         const int P = 2 * (ny - 1);
-        if (ra >= 0 && rb <= ny - 1) {
+        if (per) {
+            // Wrapped rows may come from either end of the grid (the host
+            // runs this only where the whole grid fits a buffer range).
+            base_row = 0;
+            top_row = ny;
+        } else if (ra >= 0 && rb <= ny - 1) {
             base_row = ra;
             top_row = rb + 1;
         } else if (rb - ra + 1 < P && ra < 0 && rb <= ny - 1 && -ra <= ny - 1) {
@@ -576,7 +596,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     // Level-0 row jj (window fields) and the point field at point_row(jj).
     auto issue_loads = [&](int jj, auto& v, auto& p) {
         int jr = jj;
-        if constexpr (BND) (void)reflect(jj, ny, jr);
+        if constexpr (BND) (void)map_node(jj, ny, per, jr);
         const uint32_t so = (uint32_t)((jr - base_row) * row_bytes);
         constexpr int off = (sizeof(v[0]) / sizeof(T) == E) ? CB : 0;  // window rows carry the extension
 #pragma unroll
@@ -589,7 +609,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
         if constexpr (DEPTH == 1) {
             if (!st_lane) return;
         }
-        if constexpr (BND) (void)reflect(jp, ny, jp);
+        if constexpr (BND) (void)map_node(jp, ny, per, jp);
         const Vec<T, CW> x = buf_load<T, CW>(rs_pin, voff, (uint32_t)((jp - base_row) * row_bytes));
 #pragma unroll
         for (int m = 0; m < CW; ++m) p[m] = x.v[m];
@@ -611,13 +631,15 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     auto phase = [&](int ph, int j, bool warm) {
         // Finish level-0 row j and its point-field row (loaded one row ago).
         if constexpr (BND) {
-            int jr;
-            const int sy = reflect(j, ny, jr);
+            if (!per) {
+                int jr;
+                const int sy = reflect(j, ny, jr);
 #pragma unroll
-            for (int f = 0; f < NW; ++f) reflect_vals(win[0][ph][f][CB], win[0][ph][f][CB + 1], sy);
-            const int sp = reflect(point_row(j), ny, jr);
-            T(&p)[CW] = pf[0][mod_c(ph - R, NS)];
-            reflect_vals(p[0], p[1], sp);
+                for (int f = 0; f < NW; ++f) reflect_vals(win[0][ph][f][CB], win[0][ph][f][CB + 1], sy);
+                const int sp = reflect(point_row(j), ny, jr);
+                T(&p)[CW] = pf[0][mod_c(ph - R, NS)];
+                reflect_vals(p[0], p[1], sp);
+            }
         }
         if constexpr (EXT) extend_row<T, NW, CW, R>(win[0][ph]);
         // Levels 1..DEPTH at rows j - t*R; the next row enters the window

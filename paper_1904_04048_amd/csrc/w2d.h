@@ -12,6 +12,7 @@ namespace w2d {
 
 struct Grid {
     int nx, ny, ld;
+    int periodic = 0;  // boundary rule: 0 Dirichlet (odd reflection), 1 periodic with period nx, ny
 };
 
 // Two-step weights (2 x the A-operator node weights).

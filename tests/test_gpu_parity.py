@@ -231,14 +231,27 @@ def test_f32c_init_export_roundtrip():
     w.wave2d_f32c_init(B, A, u, lo, d)
     out = torch.empty_like(A)
     w.wave2d_f32c_export(u, lo, out)
-    ref = a.copy()
-    ref[0, :] = ref[-1, :] = ref[:, 0] = ref[:, -1] = 0
+    # every node converted; u + lo carries ~48 bits of the FP64 value
     got = out.cpu().numpy()
-    # u + lo carries ~48 bits of the FP64 value
-    assert np.max(np.abs(got - ref)) <= 2.0 ** -46 * np.max(np.abs(ref))
-    dd = (a - b).astype(np.float32)
-    dd[0, :] = dd[-1, :] = dd[:, 0] = dd[:, -1] = 0
-    assert np.array_equal(d.cpu().numpy(), dd)
+    assert np.max(np.abs(got - a)) <= 2.0 ** -46 * np.max(np.abs(a))
+    assert np.array_equal(d.cpu().numpy(), (a - b).astype(np.float32))
+    # A Dirichlet step reads the boundary nodes as 0 whatever they hold and
+    # writes 0 there: same state as from inputs with zeroed boundaries.
+    az, bz = a.copy(), b.copy()
+    for z in (az, bz):
+        z[0, :] = z[-1, :] = z[:, 0] = z[:, -1] = 0
+    uz, loz, dz = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
+    w.wave2d_f32c_init(dev_grid(bz), dev_grid(az), uz, loz, dz)
+    h = 1.0 / 44
+    tau = 0.5 * w.wave2d_lambda_max(w.P13) * h
+    for simple in (True, False):
+        st = [t.clone() for t in (u, lo, d, uz, loz, dz)]
+        fl = w.KERNEL_SIMPLE if simple else 0
+        w.wave2d_f32c_step(st[0], st[1], st[2], h, tau, 1.0, w.P13, 3, fl)
+        w.wave2d_f32c_step(st[3], st[4], st[5], h, tau, 1.0, w.P13, 3, fl)
+        for x, y in zip(st[:3], st[3:]):
+            assert torch.equal(x, y)
+            assert not x[0].any() and not x[-1].any() and not x[:, 0].any() and not x[:, -1].any()
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (3, 700), (1025, 513), (300, 257)])

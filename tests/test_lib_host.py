@@ -115,6 +115,7 @@ def _step(L, nx=10, ny=10, ld=10, h=0.1, tau=0.05, c=1.0, scheme=5, flags=0, ste
     (dict(a=ctypes.c_void_p(0)), -1), (dict(b=FAKE), -1),
     (dict(tau=0.0708), -2), (dict(scheme=13, tau=0.0708), -2), (dict(scheme=9, tau=0.0797), -2),
     (dict(nx=50000, ny=50000, ld=50000), -1), (dict(ld=(1 << 22) + 1), -1),
+    (dict(flags=0x4, nx=4, ny=9, ld=4, scheme=13), -1),  # periodic 13-point needs 5 x 5 nodes
 ])
 def test_validation_rejects(L, kw, code):
     assert _step(L, **kw) == code
