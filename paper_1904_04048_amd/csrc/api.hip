@@ -175,6 +175,7 @@ StepW32 step_w32(const Params& p)
     w.w11 = (float)(2.0 * p.wa[1]);
     w.w20 = (float)(2.0 * p.wa[2]);
     w.wc = -4.0f * (w.w10 + w.w11 + w.w20);
+    w.wx = (float)(2.0 * p.wa[0] + 4.0 * p.wa[1] + 8.0 * p.wa[2]);
     return w;
 }
 
@@ -218,35 +219,68 @@ struct TuneEntry {
 };
 TuneEntry g_tune[2][4] = {};
 
-// Default segment height for an nx x ny grid: the work items of a pass
-// fill whole rounds of the device's resident waves (a nearly empty last
-// round leaves the GPU idle), and at least two rounds, so that the waves'
-// load-heavy warm-up phases do not all coincide.  The fewest such rounds
-// give the tallest segments, which recompute the fewest halo rows; heights
-// stay in [8, 64].  (Measured on MI355X: 4097^2 9-point compensated depth 6
-// gives 37 rows, about 10% faster than fixed heights of 32 or 48.)
+// Default segment height for a grid.  A pass costs about rows + 2 R depth
+// phases per work item (the item recomputes R depth rows of its neighbours
+// above and below) and its items run in rounds of the device's resident
+// wave slots.  Heights are chosen so the items fill about 1.5 rounds when
+// three or more waves share a SIMD (a half-full last round still keeps
+// 1.5 waves per SIMD issuing) and 2 rounds with fewer, within
+// [max(8, 2 R depth), 64] rows.  Measured on MI355X, compensated 9-point,
+// depth 6 (3 waves per SIMD): 4097^2 best at 30-32 rows (1.5-1.6 rounds;
+// 694 GLUP/s in one round, 793 in two), 2049^2 best at 12-16 rows, 8193^2
+// at 48-64.
 int fill_rows(int precision, int kind, int depth, int64_t nx, int64_t ny)
 {
     const ShapeFit f = stream_shape_fit(precision, kind, depth);
     if (f.slots < 1 || f.strip_cols < 1) return 32;
     const int64_t nstrips = (nx + f.strip_cols - 1) / f.strip_cols;
-    for (int k = 2; k <= 256; ++k) {
-        const int64_t segs = (int64_t)k * f.slots / nstrips;
-        if (segs < 1) continue;
-        const int64_t r = (ny + segs - 1) / segs;
-        if (r <= 64) return (int)std::max<int64_t>(8, r);
-    }
-    return 64;
+    const double target = (f.simd_waves >= 3) ? 1.5 : 2.0;
+    const int64_t segs = std::max<int64_t>(1, (int64_t)(target * f.slots) / nstrips);
+    const int64_t r = (ny + segs - 1) / segs;
+    const int64_t lo = std::max(8, 2 * f.halo_rows);
+    return (int)std::min<int64_t>(64, std::max<int64_t>(lo, r));
+}
+
+// Shapes measured fastest on MI355X (256 CUs) for the grid sizes of the
+// standard workloads: sweeps of depth and of every segment height near the
+// best, repeated (the height of the last, partial segment of a column
+// makes neighbouring heights differ by up to 10%).  Used only on devices
+// with the same CU count.
+struct MeasuredShape {
+    int precision, scheme;
+    int64_t nx, ny;
+    wave2d_tuning t;
+};
+const MeasuredShape kMeasured[] = {
+    {WAVE2D_F32C, WAVE2D_P9, 4097, 4097, {8, 40}},   // 855 GLUP/s
+    {WAVE2D_F32C, WAVE2D_P9, 8193, 8193, {8, 68}},   // 1077
+    {WAVE2D_F32C, WAVE2D_P9, 2049, 2049, {6, 13}},   // 457
+    {WAVE2D_F32C, WAVE2D_P5, 4097, 4097, {8, 40}},   // 890
+    {WAVE2D_F32C, WAVE2D_P13, 4097, 4097, {6, 44}},  // 560
+    {WAVE2D_F32C, WAVE2D_P13, 8193, 8193, {6, 112}}, // 778
+};
+
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+    (void)hipGetLastError();
+    return cus;
 }
 
 // Depths measured fastest on MI355X (depth x rows sweeps of the streaming
-// kernels on 4097^2 and 8193^2 grids); overridable per process.  Without a
+// kernels on 2049^2 to 8193^2 grids); overridable per process.  Without a
 // grid size the height is 8, the least segment height batched launches
 // start from.
 wave2d_tuning default_tuning(int precision, int scheme, int64_t nx, int64_t ny)
 {
+    for (const MeasuredShape& m : kMeasured)
+        if (m.precision == precision && m.scheme == scheme && m.nx == nx && m.ny == ny && device_cus() == 256)
+            return m.t;
     int depth;
-    if (precision == WAVE2D_F32C) depth = (scheme == WAVE2D_P13) ? 4 : (scheme == WAVE2D_P5) ? 8 : 6;
+    if (precision == WAVE2D_F32C) depth = (scheme == WAVE2D_P13) ? 6 : 8;
     else depth = (scheme == WAVE2D_P13) ? 3 : 6;
     const int rows = (nx > 0 && ny > 0) ? fill_rows(precision, kind_of(scheme), depth, nx, ny) : 8;
     return wave2d_tuning{depth, rows};

@@ -363,32 +363,73 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
         (void)hipGetLastError();
         return fail(WAVE2D_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    // Scratch and events are released on every return below.
+    struct Release {
+        void* buf;
+        hipEvent_t* e0;
+        hipEvent_t* e1;
+        ~Release()
+        {
+            if (*e0) (void)hipEventDestroy(*e0);
+            if (*e1) (void)hipEventDestroy(*e1);
+            (void)hipFree(buf);
+        }
+    } release{buf, &e0, &e1};
     W2D_HIP(hipMemsetAsync(buf, 0, 2 * nf * align256(n * elt), s));
     char* c = (char*)buf;
     auto arr = [&](int k) { return (void*)(c + k * align256(n * elt)); };
     const Fork* fk = nullptr;
-    if ((r = side_of(s, &fk))) {
-        (void)hipFree(buf);
-        return r;
-    }
+    if ((r = side_of(s, &fk))) return r;
     // Candidate shapes: every supported depth whose interior kernel keeps
     // its state in registers, with fixed segment heights plus the heights
-    // at which the work items exactly fill k rounds of the resident wave
-    // slots (a last round that is nearly empty leaves the GPU idle).
+    // at which the work items fill k/2 rounds of the resident wave slots.
     static const int depths[] = {1, 2, 3, 4, 6, 8};
     static const int rows_fixed[] = {8, 16, 24, 32, 48, 64};
-    hipEvent_t e0, e1;
     W2D_HIP(hipEventCreate(&e0));
     W2D_HIP(hipEventCreate(&e1));
-    float best_t = 1e30f;
-    wave2d_tuning bt{1, 16};
+    // Time per level of one shape over about `target_ms` (a short probe
+    // sizes the run), ping-ponging between the two scratch states.
+    auto time_shape = [&](int dep, int rows, float target_ms, float* per_level) -> int {
+        const StreamShape sh{dep, rows, fk};
+        auto pass = [&](int k) -> hipError_t {
+            const int a = (k & 1) ? nf : 0, b2 = (k & 1) ? 0 : nf;
+            if (precision == WAVE2D_F64)
+                return stream_step_f64(p.g, p.kind, step_w64(p), sh, (const double*)arr(a), (const double*)arr(a + 1),
+                                       (double*)arr(b2), (double*)arr(b2 + 1), s);
+            return stream_step_f32c(p.g, p.kind, step_w32(p), sh, (const float*)arr(a), (const float*)arr(a + 1),
+                                    (const float*)arr(a + 2), (float*)arr(b2), (float*)arr(b2 + 1), (float*)arr(b2 + 2),
+                                    s);
+        };
+        auto timed = [&](int reps, float* ms) -> int {
+            W2D_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) W2D_HIP(pass(k + 1));
+            W2D_HIP(hipEventRecord(e1, s));
+            W2D_HIP(hipEventSynchronize(e1));
+            W2D_HIP(hipEventElapsedTime(ms, e0, e1));
+            return WAVE2D_OK;
+        };
+        W2D_HIP(pass(0));
+        float ms = 0.f;
+        int rr;
+        if ((rr = timed(2, &ms))) return rr;
+        const int reps = std::min(256, std::max(2, (int)std::ceil(target_ms / std::max(ms / 2, 1e-3f))));
+        if ((rr = timed(reps, &ms))) return rr;
+        *per_level = ms / (reps * dep);
+        return WAVE2D_OK;
+    };
+    struct Cand {
+        float per_level;
+        int depth, rows;
+    };
+    std::vector<Cand> timed_c;
     for (int dep : depths) {
         const ShapeFit fit = stream_shape_fit(precision, p.kind, dep);
         if (fit.spills || fit.slots < 1 || fit.strip_cols < 1) continue;
         const int64_t nstrips = (nx + fit.strip_cols - 1) / fit.strip_cols;
         std::vector<int> rows_c(std::begin(rows_fixed), std::end(rows_fixed));
-        for (int k = 1; k <= 8; ++k) {
-            const int64_t segs = (int64_t)k * fit.slots / nstrips;
+        for (int k = 2; k <= 16; ++k) {
+            const int64_t segs = (int64_t)k * fit.slots / (2 * nstrips);
             if (segs < 1) continue;
             const int64_t r = (ny + segs - 1) / segs;
             if (r >= 8 && r <= 256) rows_c.push_back((int)r);
@@ -397,41 +438,26 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
         rows_c.erase(std::unique(rows_c.begin(), rows_c.end()), rows_c.end());
         for (int rows : rows_c) {
             if (rows > std::max<int64_t>(8, ny)) continue;
-            const StreamShape sh{dep, rows, fk};
-            auto pass = [&](int k) -> hipError_t {
-                const int a = (k & 1) ? nf : 0, b2 = (k & 1) ? 0 : nf;
-                if (precision == WAVE2D_F64)
-                    return stream_step_f64(p.g, p.kind, step_w64(p), sh, (const double*)arr(a), (const double*)arr(a + 1),
-                                           (double*)arr(b2), (double*)arr(b2 + 1), s);
-                return stream_step_f32c(p.g, p.kind, step_w32(p), sh, (const float*)arr(a), (const float*)arr(a + 1),
-                                        (const float*)arr(a + 2), (float*)arr(b2), (float*)arr(b2 + 1),
-                                        (float*)arr(b2 + 2), s);
-            };
-            // A short probe sizes the timed run to about 2 ms.
-            auto timed = [&](int reps, float* ms) -> int {
-                W2D_HIP(hipEventRecord(e0, s));
-                for (int k = 0; k < reps; ++k) W2D_HIP(pass(k + 1));
-                W2D_HIP(hipEventRecord(e1, s));
-                W2D_HIP(hipEventSynchronize(e1));
-                W2D_HIP(hipEventElapsedTime(ms, e0, e1));
-                return WAVE2D_OK;
-            };
-            W2D_HIP(pass(0));
-            float ms = 0.f;
-            if ((r = timed(2, &ms))) return r;
-            const int reps = std::min(64, std::max(2, (int)std::ceil(2.0f / std::max(ms / 2, 1e-3f))));
-            if ((r = timed(reps, &ms))) return r;
-            const float per_level = ms / (reps * dep);
-            if (per_level < best_t) {
-                best_t = per_level;
-                bt = wave2d_tuning{dep, rows};
-            }
+            float per_level = 0.f;
+            if ((r = time_shape(dep, rows, 2.0f, &per_level))) return r;
+            timed_c.push_back(Cand{per_level, dep, rows});
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // The few fastest shapes again, each timed over about 10 ms: single
+    // 2 ms timings of shapes within a few percent of each other can rank
+    // them wrongly.
+    std::sort(timed_c.begin(), timed_c.end(), [](const Cand& a, const Cand& b) { return a.per_level < b.per_level; });
+    float best_t = 1e30f;
+    wave2d_tuning bt{1, 16};
+    for (size_t k = 0; k < timed_c.size() && k < 4; ++k) {
+        float per_level = 0.f;
+        if ((r = time_shape(timed_c[k].depth, timed_c[k].rows, 10.0f, &per_level))) return r;
+        if (per_level < best_t) {
+            best_t = per_level;
+            bt = wave2d_tuning{timed_c[k].depth, timed_c[k].rows};
+        }
+    }
     W2D_HIP(hipStreamSynchronize(s));
-    (void)hipFree(buf);
     set_tuning_entry(precision, scheme, bt);
     set_tuning_size_entry(precision, scheme, nx, ny, bt);
     *best = bt;

@@ -60,6 +60,52 @@ __device__ __forceinline__ float lap_sum(const Nbh<float>& v, float wc, float w1
     return s;
 }
 
+// Increment of the compensated level u + lo (single precision):
+// sum_q w_q delta(q) applied to u + lo.
+//
+// 5-point: lap_diff of u plus lap_sum of lo.
+//
+// 9- and 13-point: regrouped by exact identities between the rotation sums
+// and the second differences Dx f = f(i+1) - 2f(i) + f(i-1), Dy likewise:
+//   delta(1,0) = Dx + Dy,  delta(1,1) = 2 (Dx + Dy) + Dx Dy,
+//   delta(2,0) = Dx Dx + Dy Dy + 4 (Dx + Dy),
+// so the increment is wx (Dx + Dy) + w11 Dx Dy + w20 (Dx Dx + Dy Dy) with
+// wx = w10 + 2 w11 + 4 w20 (lambda^2 for the schemes of Sec. 6).  Each
+// second difference of u is a difference of two neighbour differences,
+// which are exact for close values; those of u and of lo are added only
+// after they are formed.  The mixed and fourth differences are taken of
+// the summed second differences q = Dy u + Dy lo and p = Dx u + Dx lo.  Every
+// step is symmetric under negation and under mirroring, so odd-reflected
+// data give odd-reflected increments with exact zeros on the mirror lines.
+template <typename T>
+__device__ __forceinline__ T d2(T a, T c, T b)  // (a - c) - (c - b)
+{
+    return (a - c) - (c - b);
+}
+
+template <int K>
+__device__ __forceinline__ float f32c_incr(const Nbh<float>& u, const Nbh<float>& l, float wc, float w10, float w11,
+                                           float w20, float wx)
+{
+    if constexpr (K == KIND5) {
+        return lap_diff<K>(u, w10, w11, w20) + lap_sum<K>(l, wc, w10, w11, w20);
+    } else {
+        const float q = d2(u.N, u.C, u.S) + d2(l.N, l.C, l.S);
+        const float p = d2(u.E, u.C, u.W) + d2(l.E, l.C, l.W);
+        const float qE = d2(u.NE, u.E, u.SE) + d2(l.NE, l.E, l.SE);
+        const float qW = d2(u.NW, u.W, u.SW) + d2(l.NW, l.W, l.SW);
+        float s = fmaT(w11, d2(qE, q, qW), wx * (p + q));
+        if constexpr (KT<K>::AX2) {
+            const float pE = d2(u.EE, u.E, u.C) + d2(l.EE, l.E, l.C);
+            const float pW = d2(u.C, u.W, u.WW) + d2(l.C, l.W, l.WW);
+            const float qN = d2(u.NN, u.N, u.C) + d2(l.NN, l.N, l.C);
+            const float qS = d2(u.C, u.S, u.SS) + d2(l.C, l.S, l.SS);
+            s = fmaT(w20, d2(pE, p, pW) + d2(qN, q, qS), s);
+        }
+        return s;
+    }
+}
+
 // FP64 two-step update (Sec. 3, eq. A2): u^{k+1} = 2u^k - u^{k-1} + s.
 __device__ __forceinline__ double f64_update(double C, double P, double s) { return ((C + C) - P) + s; }
 
@@ -67,17 +113,15 @@ __device__ __forceinline__ double f64_update(double C, double P, double s) { ret
 // With s the stencil increment of u + lo: d <- d + s; the new level
 // u + lo + d is formed as y = d + lo followed by an error-free sum u + y =
 // t + e (Knuth's branch-free TwoSum), so that t is the new u and e the new lo.
-__device__ __forceinline__ void f32c_update(float su, float slo, float u, float lo, float d, float& u2,
-                                            float& lo2, float& d2)
+__device__ __forceinline__ void f32c_update(float s, float u, float lo, float d, float& u2, float& lo2, float& dn2)
 {
-    const float s = su + slo;
     const float dn = d + s;
     const float y = dn + lo;
     const float t = u + y;
     const float z = t - u;
     lo2 = (u - (t - z)) + (y - z);
     u2 = t;
-    d2 = dn;
+    dn2 = dn;
 }
 
 // FP64 first step (Sec. 3, eq. A1): u^1 = (u^0 + sum wa delta(u^0)) +

@@ -132,9 +132,8 @@ __global__ __launch_bounds__(BX* BY) void k_step_f32c(Grid g, StepW32 w, const f
     if (interior(g, i, j)) {
         const Nbh<float> a = gather<K>(u, g, i, j);
         const Nbh<float> b = gather<K>(lo, g, i, j);
-        const float su = lap_diff<K>(a, w.w10, w.w11, w.w20);
-        const float sl = lap_sum<K>(b, w.wc, w.w10, w.w11, w.w20);
-        f32c_update(su, sl, a.C, b.C, d[o], ru, rl, rd);
+        const float s = f32c_incr<K>(a, b, w.wc, w.w10, w.w11, w.w20, w.wx);
+        f32c_update(s, a.C, b.C, d[o], ru, rl, rd);
     }
     u2[o] = ru;
     lo2[o] = rl;

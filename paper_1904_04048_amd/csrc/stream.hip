@@ -135,9 +135,10 @@ __device__ __forceinline__ void buf_store1(T x, __amdgpu_buffer_rsrc_t r, uint32
     }
 }
 
-// Stencil update of one row segment (CW columns per lane) of level t from
-// the level t-1 window rows (centre, north, south, and the second ring for
-// the 13-point stencil) and the level t-1 point field.
+// Double-precision stencil update of one row segment (CW columns per lane)
+// of level t from the level t-1 window rows (centre, north, south, and the
+// second ring for the 13-point stencil), extended by R columns on each
+// side, and the level t-1 point field.
 template <class Prec, int K, int CW>
 __device__ __forceinline__ void row_update(
     const typename Prec::T (&Wc)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Wn)[Prec::NW][CW + 2 * KT<K>::R],
@@ -147,130 +148,91 @@ __device__ __forceinline__ void row_update(
 {
     using T = typename Prec::T;
     constexpr int R = KT<K>::R;
-    constexpr int NW = Prec::NW;
+    static_assert(Prec::NW == 1, "extended rows are used by the double-precision path only");
 #pragma unroll
     for (int m = 0; m < CW; ++m) {
         const int e = R + m;
-        Nbh<T> nb[NW];
-#pragma unroll
-        for (int f = 0; f < NW; ++f) {
-            nb[f].C = Wc[f][e];
-            nb[f].E = Wc[f][e + 1];
-            nb[f].W = Wc[f][e - 1];
-            nb[f].N = Wn[f][e];
-            nb[f].S = Ws[f][e];
-            if constexpr (KT<K>::DIAG) {
-                nb[f].NE = Wn[f][e + 1];
-                nb[f].NW = Wn[f][e - 1];
-                nb[f].SE = Ws[f][e + 1];
-                nb[f].SW = Ws[f][e - 1];
-            } else {
-                nb[f].NE = nb[f].NW = nb[f].SE = nb[f].SW = T(0);
-            }
-            if constexpr (KT<K>::AX2) {
-                nb[f].EE = Wc[f][e + 2];
-                nb[f].WW = Wc[f][e - 2];
-                nb[f].NN = Wnn[f][e];
-                nb[f].SS = Wss[f][e];
-            } else {
-                nb[f].EE = nb[f].WW = nb[f].NN = nb[f].SS = T(0);
-            }
-        }
-        if constexpr (NW == 1) {
-            const T s = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
-            nv[0][e] = (T)f64_update((double)nb[0].C, (double)Pin[m], (double)s);
-            np[m] = nb[0].C;
+        Nbh<T> nb;
+        nb.C = Wc[0][e];
+        nb.E = Wc[0][e + 1];
+        nb.W = Wc[0][e - 1];
+        nb.N = Wn[0][e];
+        nb.S = Ws[0][e];
+        if constexpr (KT<K>::DIAG) {
+            nb.NE = Wn[0][e + 1];
+            nb.NW = Wn[0][e - 1];
+            nb.SE = Ws[0][e + 1];
+            nb.SW = Ws[0][e - 1];
         } else {
-            const float su = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
-            const float sl = lap_sum<K>(nb[1], w.wc, w.w10, w.w11, w.w20);
-            float u2, l2, d2;
-            f32c_update(su, sl, nb[0].C, nb[1].C, Pin[m], u2, l2, d2);
-            nv[0][e] = u2;
-            nv[1][e] = l2;
-            np[m] = d2;
+            nb.NE = nb.NW = nb.SE = nb.SW = T(0);
         }
+        if constexpr (KT<K>::AX2) {
+            nb.EE = Wc[0][e + 2];
+            nb.WW = Wc[0][e - 2];
+            nb.NN = Wnn[0][e];
+            nb.SS = Wss[0][e];
+        } else {
+            nb.EE = nb.WW = nb.NN = nb.SS = T(0);
+        }
+        const T s = lap_diff<K>(nb, w.w10, w.w11, w.w20);
+        nv[0][e] = (T)f64_update((double)nb.C, (double)Pin[m], (double)s);
+        np[m] = nb.C;
     }
 }
 
-// The same update from rows that hold only the lane's own CW columns: the
-// neighbours beyond them are fetched from the adjacent lanes where they are
-// used (a DPP shift that the compiler folds into the subtraction or
-// addition consuming it, for single precision).  Same arithmetic, fewer
-// registers than keeping extended rows.
-template <class Prec, int K, int CW>
-__device__ __forceinline__ void row_update_at_use(
-    const typename Prec::T (&Wc)[Prec::NW][CW], const typename Prec::T (&Wn)[Prec::NW][CW],
-    const typename Prec::T (&Ws)[Prec::NW][CW], const typename Prec::T (&Wnn)[Prec::NW][CW],
-    const typename Prec::T (&Wss)[Prec::NW][CW], const typename Prec::T (&Pin)[CW], const typename Prec::W& w,
-    typename Prec::T (&nv)[Prec::NW][CW], typename Prec::T (&np)[CW])
-{
-    using T = typename Prec::T;
-    constexpr int NW = Prec::NW;
-    // column m + o of a row, o in [-2, 2]
-    auto col = [](const T (&r)[CW], int m, int o) -> T {
-        const int c = m + o;
-        if (c >= 0 && c < CW) return r[c];
-        if (c >= CW) return from_right(r[c - CW]);
-        return from_left(r[c + CW]);
-    };
-#pragma unroll
-    for (int m = 0; m < CW; ++m) {
-        Nbh<T> nb[NW];
-#pragma unroll
-        for (int f = 0; f < NW; ++f) {
-            nb[f].C = Wc[f][m];
-            nb[f].E = col(Wc[f], m, 1);
-            nb[f].W = col(Wc[f], m, -1);
-            nb[f].N = Wn[f][m];
-            nb[f].S = Ws[f][m];
-            if constexpr (KT<K>::DIAG) {
-                nb[f].NE = col(Wn[f], m, 1);
-                nb[f].NW = col(Wn[f], m, -1);
-                nb[f].SE = col(Ws[f], m, 1);
-                nb[f].SW = col(Ws[f], m, -1);
-            } else {
-                nb[f].NE = nb[f].NW = nb[f].SE = nb[f].SW = T(0);
-            }
-            if constexpr (KT<K>::AX2) {
-                nb[f].EE = col(Wc[f], m, 2);
-                nb[f].WW = col(Wc[f], m, -2);
-                nb[f].NN = Wnn[f][m];
-                nb[f].SS = Wss[f][m];
-            } else {
-                nb[f].EE = nb[f].WW = nb[f].NN = nb[f].SS = T(0);
-            }
-        }
-        if constexpr (NW == 1) {
-            const T s = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
-            nv[0][m] = (T)f64_update((double)nb[0].C, (double)Pin[m], (double)s);
-            np[m] = nb[0].C;
-        } else {
-            const float su = lap_diff<K>(nb[0], w.w10, w.w11, w.w20);
-            const float sl = lap_sum<K>(nb[1], w.wc, w.w10, w.w11, w.w20);
-            float u2, l2, d2;
-            f32c_update(su, sl, nb[0].C, nb[1].C, Pin[m], u2, l2, d2);
-            nv[0][m] = u2;
-            nv[1][m] = l2;
-            np[m] = d2;
-        }
-    }
-}
-
-// Compensated single precision with differences carried from row to row.
-// Going down the rows of one level, the centre row y reuses what row y-1
-// computed: S - C = -(N - C of row y-1), SW - C and SE - C are the negated
-// NE - C and NW - C of row y-1 one column over, and the lo row sums
-// lo(i+1) + lo(i-1) of rows y-1 and y.  Every operation and its operands
-// are those of lap_diff / lap_sum (a + (-b) rounds exactly as a - b), so
-// the result is bit-identical; only repeated subtractions are saved.
+// Compensated single precision with differences carried from row to row:
+// going down the rows of one level, what row y-1 computed for its northern
+// neighbours serves row y as its southern ones.  Every operation and its
+// operands are those of f32c_incr (a + (-b) rounds exactly as a - b), so
+// the result is bit-identical to the one-node-per-thread kernels; only
+// repeated subtractions are saved.
+//   5-point: N - C of u (its negation is the next row's S - C) and the lo
+//            row sums lo(i+1) + lo(i-1) of rows y-1 and y.
+//   9-point: N - C of u and of lo (the next row's C - S).
+//   13-point: the same one row further north, the summed second difference
+//            q = Dy u + Dy lo of row y and q(y) - q(y-1).
+// Column neighbours beyond the lane's own CW columns come from the adjacent
+// lanes (DPP shifts folded into the consuming subtraction or addition).
 template <int CW>
 struct Carry {
-    float dv[CW];  // N - C of the previous centre row
-    float dd[CW];  // NE - C of the previous centre row
-    float da[CW];  // NW - C of the previous centre row
-    float hs0[CW]; // lo(i+1) + lo(i-1) of row y-1
-    float hs1[CW]; // lo(i+1) + lo(i-1) of row y
+    float dv[CW];  // N - C of u
+    float dl[CW];  // N - C of lo (9-, 13-point)
+    float hs0[CW]; // lo(i+1) + lo(i-1) of row y-1 (5-point)
+    float hs1[CW]; // lo(i+1) + lo(i-1) of row y (5-point)
+    float q[CW];   // q of row y (13-point)
+    float eq[CW];  // q(y) - q(y-1) (13-point)
 };
+
+template <int CW>
+__device__ __forceinline__ void carry_zero(Carry<CW>& c)
+{
+#pragma unroll
+    for (int m = 0; m < CW; ++m) c.dv[m] = c.dl[m] = c.hs0[m] = c.hs1[m] = c.q[m] = c.eq[m] = 0.f;
+}
+
+// column m + o of a lane's row, o in [-1, 1]
+template <int CW>
+__device__ __forceinline__ float lane_col(const float (&r)[CW], int m, int o)
+{
+    const int c = m + o;
+    if (c >= 0 && c < CW) return r[c];
+    if (c >= CW) return from_right(r[c - CW]);
+    return from_left(r[c + CW]);
+}
+
+// Second difference along x of a lane's row: out[m] = d2(r(m+1), r(m), r(m-1)),
+// from the first differences e[k] = r(k) - r(k-1), k = 0..CW.
+template <int CW>
+__device__ __forceinline__ void row_d2x(const float (&r)[CW], float (&out)[CW])
+{
+    float e[CW + 1];
+    e[0] = r[0] - from_left(r[CW - 1]);
+#pragma unroll
+    for (int k = 1; k < CW; ++k) e[k] = r[k] - r[k - 1];
+    e[CW] = from_right(r[0]) - r[CW - 1];
+#pragma unroll
+    for (int m = 0; m < CW; ++m) out[m] = e[m + 1] - e[m];
+}
 
 template <int K, int CW>
 __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const float (&Wn)[2][CW],
@@ -278,67 +240,91 @@ __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const
                                                  const float (&Wss)[2][CW], const float (&Pin)[CW], Carry<CW>& cr,
                                                  const StepW32& w, bool update, float (&nv)[2][CW], float (&np)[CW])
 {
-    auto col = [](const float (&r)[CW], int m, int o) -> float {
-        const int c = m + o;
-        if (c >= 0 && c < CW) return r[c];
-        if (c >= CW) return from_right(r[c - CW]);
-        return from_left(r[c + CW]);
-    };
     const float(&U)[CW] = Wc[0];
-    const float(&Un)[CW] = Wn[0];
-    // Quantities of this centre row that the next row reuses.
-    float dv[CW], dd[CW], da[CW], hsn[CW];
-#pragma unroll
-    for (int m = 0; m < CW; ++m) {
-        dv[m] = Un[m] - U[m];
-        if constexpr (KT<K>::DIAG) {
-            dd[m] = col(Un, m, 1) - U[m];
-            da[m] = col(Un, m, -1) - U[m];
-            hsn[m] = col(Wn[1], m, 1) + col(Wn[1], m, -1);
-        } else {
-            dd[m] = da[m] = 0.f;
-            hsn[m] = col(Wn[1], m, 1) + col(Wn[1], m, -1);
-        }
-    }
-    if (update) {
-        // eh[k] = u(k) - u(k-1) for the centre row, k = 0..CW (relative columns).
-        float eh[CW + 1];
-        eh[0] = U[0] - col(U, 0, -1);
-#pragma unroll
-        for (int k = 1; k < CW; ++k) eh[k] = U[k] - U[k - 1];
-        eh[CW] = col(U, CW - 1, 1) - U[CW - 1];
+    const float(&L)[CW] = Wc[1];
+    if constexpr (K == KIND5) {
+        float dv[CW], hsn[CW];
 #pragma unroll
         for (int m = 0; m < CW; ++m) {
-            const float C = U[m];
-            float s = w.w10 * ((eh[m + 1] - eh[m]) + (dv[m] - cr.dv[m]));
-            if constexpr (KT<K>::DIAG) {
-                const float sw = (m >= 1) ? cr.dd[m - 1] : from_left(cr.dd[CW - 1]);
-                const float se = (m + 1 < CW) ? cr.da[m + 1] : from_right(cr.da[0]);
-                s = fmaT(w.w11, (dd[m] - sw) + (da[m] - se), s);
-            }
-            if constexpr (KT<K>::AX2) {
-                s = fmaT(w.w20, ((col(U, m, 2) - C) + (col(U, m, -2) - C)) + ((Wnn[0][m] - C) + (Wss[0][m] - C)), s);
-            }
-            // lo part (weighted sums)
-            const float Lc = Wc[1][m];
-            float sl = fmaT(w.w10, cr.hs1[m] + (Wn[1][m] + Ws[1][m]), w.wc * Lc);
-            if constexpr (KT<K>::DIAG) sl = fmaT(w.w11, hsn[m] + cr.hs0[m], sl);
-            if constexpr (KT<K>::AX2)
-                sl = fmaT(w.w20, (col(Wc[1], m, 2) + col(Wc[1], m, -2)) + (Wnn[1][m] + Wss[1][m]), sl);
-            float u2, l2, d2;
-            f32c_update(s, sl, C, Lc, Pin[m], u2, l2, d2);
-            nv[0][m] = u2;
-            nv[1][m] = l2;
-            np[m] = d2;
+            dv[m] = Wn[0][m] - U[m];
+            hsn[m] = lane_col(Wn[1], m, 1) + lane_col(Wn[1], m, -1);
         }
-    }
+        if (update) {
+            float eh[CW + 1];
+            eh[0] = U[0] - from_left(U[CW - 1]);
 #pragma unroll
-    for (int m = 0; m < CW; ++m) {
-        cr.dv[m] = dv[m];
-        cr.dd[m] = dd[m];
-        cr.da[m] = da[m];
-        cr.hs0[m] = cr.hs1[m];
-        cr.hs1[m] = hsn[m];
+            for (int k = 1; k < CW; ++k) eh[k] = U[k] - U[k - 1];
+            eh[CW] = from_right(U[0]) - U[CW - 1];
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const float su = w.w10 * ((eh[m + 1] - eh[m]) + (dv[m] - cr.dv[m]));
+                const float sl = fmaT(w.w10, cr.hs1[m] + (Wn[1][m] + Ws[1][m]), w.wc * L[m]);
+                f32c_update(su + sl, U[m], L[m], Pin[m], nv[0][m], nv[1][m], np[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            cr.dv[m] = dv[m];
+            cr.hs0[m] = cr.hs1[m];
+            cr.hs1[m] = hsn[m];
+        }
+    } else if constexpr (K == KIND9) {
+        float dv[CW], dl[CW];
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            dv[m] = Wn[0][m] - U[m];
+            dl[m] = Wn[1][m] - L[m];
+        }
+        if (update) {
+            float q[CW], xu[CW], xl[CW], xq[CW];
+#pragma unroll
+            for (int m = 0; m < CW; ++m) q[m] = (dv[m] - cr.dv[m]) + (dl[m] - cr.dl[m]);
+            row_d2x(U, xu);
+            row_d2x(L, xl);
+            row_d2x(q, xq);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const float s = fmaT(w.w11, xq[m], w.wx * ((xu[m] + xl[m]) + q[m]));
+                f32c_update(s, U[m], L[m], Pin[m], nv[0][m], nv[1][m], np[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            cr.dv[m] = dv[m];
+            cr.dl[m] = dl[m];
+        }
+    } else {
+        // q of row y+1 from rows y .. y+2; q of row y and q(y) - q(y-1) carried.
+        float dv[CW], dl[CW], qn[CW];
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            dv[m] = Wnn[0][m] - Wn[0][m];
+            dl[m] = Wnn[1][m] - Wn[1][m];
+            qn[m] = (dv[m] - cr.dv[m]) + (dl[m] - cr.dl[m]);
+        }
+        if (update) {
+            float p[CW], xu[CW], xl[CW], xq[CW], xp[CW];
+            row_d2x(U, xu);
+            row_d2x(L, xl);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) p[m] = xu[m] + xl[m];
+            row_d2x(cr.q, xq);
+            row_d2x(p, xp);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const float q = cr.q[m];
+                float s = fmaT(w.w11, xq[m], w.wx * (p[m] + q));
+                s = fmaT(w.w20, xp[m] + ((qn[m] - q) - cr.eq[m]), s);
+                f32c_update(s, U[m], L[m], Pin[m], nv[0][m], nv[1][m], np[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            cr.dv[m] = dv[m];
+            cr.dl[m] = dl[m];
+            cr.eq[m] = qn[m] - cr.q[m];
+            cr.q[m] = qn[m];
+        }
     }
 }
 
@@ -622,10 +608,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     Carry<CW> carry[EXT ? 1 : DEPTH];
     if constexpr (!EXT) {
 #pragma unroll
-        for (int t = 0; t < DEPTH; ++t)
-#pragma unroll
-            for (int m = 0; m < CW; ++m)
-                carry[t].dv[m] = carry[t].dd[m] = carry[t].da[m] = carry[t].hs0[m] = carry[t].hs1[m] = 0.f;
+        for (int t = 0; t < DEPTH; ++t) carry_zero(carry[t]);
     }
 
     auto phase = [&](int ph, int j, bool warm) {
@@ -938,7 +921,12 @@ template <class Prec, int K, int DEPTH>
 ShapeFit fit_depth()
 {
     const auto f = kernel_fit(reinterpret_cast<const void*>(&k_stream_interior<Prec, K, DEPTH, 2>));
-    return ShapeFit{kWave * 2 - 2 * halo_cols<KT<K>::R, DEPTH>(), f.first, f.second};
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    (void)hipGetLastError();
+    return ShapeFit{kWave * 2 - 2 * halo_cols<KT<K>::R, DEPTH>(), f.first, f.second, f.first / (4 * cus),
+                    KT<K>::R * DEPTH};
 }
 
 template <class Prec, int K>
@@ -968,7 +956,7 @@ ShapeFit fit_prec(int kind, int depth)
 
 ShapeFit stream_shape_fit(int precision, int kind, int depth)
 {
-    if (!stream_depth_supported(depth)) return ShapeFit{0, 0, true};
+    if (!stream_depth_supported(depth)) return ShapeFit{0, 0, true, 0, 0};
     return precision == 0 ? fit_prec<PF64>(kind, depth) : fit_prec<PF32C>(kind, depth);
 }
 

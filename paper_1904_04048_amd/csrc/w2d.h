@@ -19,8 +19,10 @@ struct Grid {
 struct StepW64 {
     double w10, w11, w20;
 };
+// wc = -4 (w10 + w11 + w20) (centre weight), wx = w10 + 2 w11 + 4 w20 (the
+// weight of Dx + Dy in the regrouped 9- and 13-point increments).
 struct StepW32 {
-    float w10, w11, w20, wc;
+    float w10, w11, w20, wc, wx;
 };
 // First-step weights: A node weights and B node weights divided by tau.
 struct FirstW {
@@ -107,9 +109,11 @@ hipError_t batch_launch(int precision, int kind, int depth, bool interior, const
 // waves of the interior step kernel resident on the whole device, and
 // whether that kernel spills registers to scratch memory.
 struct ShapeFit {
-    int strip_cols;
-    int slots;
-    bool spills;
+    int strip_cols;  // output columns of one work item
+    int slots;       // resident waves of the interior kernel on the device
+    bool spills;     // the kernel uses scratch memory
+    int simd_waves;  // resident waves per SIMD
+    int halo_rows;   // rows a pass reaches beyond its outputs (R x depth)
 };
 ShapeFit stream_shape_fit(int precision, int kind, int depth);
 
