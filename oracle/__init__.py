@@ -72,6 +72,8 @@ def lib():
         L.orc_run.restype = I
         L.orc_norms.argtypes = [Lg, P, P, P]
         L.orc_norms.restype = None
+        L.orc_set_scheme.argtypes = [I, I, P, P]
+        L.orc_set_scheme.restype = I
         L.orc_set_threads.argtypes = [I]
         L.orc_set_threads.restype = None
         L.orc_get_threads.argtypes = []
@@ -107,6 +109,35 @@ def brackets(scheme: int, lam: float):
     if lib().orc_brackets(int(scheme), float(lam), _ptr(a), _ptr(b), ctypes.byref(hb)):
         raise ValueError(f"unknown scheme {scheme}")
     return a, b, bool(hb.value)
+
+
+CUSTOM_DEG = 12
+
+
+def register_scheme(scheme_id: int, weights) -> None:
+    """Make scheme_id (1000..1015) run the scheme with these node weights:
+    {node: (A, B / tau)} as polynomials in lambda ({power: coefficient}),
+    e.g. from ``derive.node_weights_for``.  One node of each class (axis 1,
+    diagonal, axis 2) gives that class's weights; a class without nodes has
+    none.  First step eq. A1, two-step update eq. A2."""
+    a = np.zeros((3, CUSTOM_DEG + 1))
+    b = np.zeros((3, CUSTOM_DEG + 1))
+    reps = {(1, 0): 0, (1, 1): 1, (2, 0): 2}
+    for q, (A, B) in weights.items():
+        key = tuple(sorted((abs(q[0]), abs(q[1])), reverse=True))
+        if key == (0, 0):
+            continue  # the centre weight is one minus the others (eq. A1, A2 as rotation sums)
+        if key not in reps:
+            if any(A.values()) or any(B.values()):
+                raise ValueError(f"node {q} carries weight outside the 13-point classes")
+            continue
+        c = reps[key]
+        for p_, v in A.items():
+            a[c, p_] = float(v)
+        for p_, v in B.items():
+            b[c, p_] = float(v)
+    if lib().orc_set_scheme(int(scheme_id), CUSTOM_DEG, _ptr(a), _ptr(b)):
+        raise ValueError(f"bad custom scheme id {scheme_id}")
 
 
 def lambda_max(scheme: int) -> float:

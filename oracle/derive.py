@@ -169,6 +169,33 @@ def node_weights(m: int):
     return out
 
 
+def node_weights_for(nodes: List[Tuple[int, int]], exps: List[Tuple[int, int]]):
+    """Node weights for an explicit stencil and monomial set (the general
+    form of Sec. 4: any unisolvent pair; Sec. 5 for the operators).
+
+    D[s][r] = mu_s(x_r) (eq. matrix1), C = D^{-1} (eq. matrix2), the basis
+    function of node r is sum_s C[r][s] mu_s (eq. Lagrange), and its weights
+    are (A phi_r, B phi_r / tau) as polynomials in lambda.  Returns
+    {node: (A, B)}; raises ValueError when D is singular."""
+    m = len(nodes)
+    if len(exps) != m:
+        raise ValueError("need as many monomials as nodes")
+    D = [[_mono(exps[s], nodes[r]) for r in range(m)] for s in range(m)]
+    C, det = _inverse(D)
+    if C is None:
+        raise ValueError("the stencil is not unisolvent for these monomials")
+    out = {}
+    for r, q in enumerate(nodes):
+        Aw: Poly = {}
+        Bw: Poly = {}
+        for s in range(m):
+            if C[r][s] != 0:
+                _add(Aw, A_monomial(*exps[s]), C[r][s])
+                _add(Bw, B_monomial(*exps[s]), C[r][s])
+        out[tuple(q)] = (Aw, Bw)
+    return out
+
+
 def evaluate(P: Poly, lam) -> float:
     return sum(float(c) * lam ** p for p, c in P.items())
 

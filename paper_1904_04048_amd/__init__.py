@@ -70,6 +70,21 @@ def wave2d_lambda_max(scheme: int) -> float:
     return v
 
 
+def wave2d_scheme_create(nodes, exps) -> int:
+    """Scheme id built from m stencil nodes (q1, q2) and m monomial
+    exponents (a1, a2) (Sec. 4-5)."""
+    nodes = [int(v) for q in nodes for v in q]
+    exps = [int(v) for e in exps for v in e]
+    if len(nodes) != len(exps):
+        raise ValueError("nodes and exps must have the same length")
+    m = len(nodes) // 2
+    nb = (ctypes.c_int32 * max(1, 2 * m))(*nodes)
+    eb = (ctypes.c_int32 * max(1, 2 * m))(*exps)
+    sid = ctypes.c_int(0)
+    _lib.check(_lib.load().wave2d_scheme_create(m, nb, eb, ctypes.byref(sid)))
+    return sid.value
+
+
 def wave2d_weights(scheme: int, lam: float, flags: int = 0):
     """(w2, wa, wb): two-step weights and first-step A / (B/tau) node weights."""
     w2, wa, wb = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_double * 3)()

@@ -64,6 +64,7 @@ class ServerStats(ctypes.Structure):
 
 _SIGS = {
     "wave2d_lambda_max": (D, [I]),
+    "wave2d_scheme_create": (I, [ctypes.c_int32, P, P, P]),
     "wave2d_weights": (I, [I, U32, D, P, P, P]),
     "wave2d_status_str": (ctypes.c_char_p, [I]),
     "wave2d_last_error": (ctypes.c_char_p, []),

@@ -52,10 +52,15 @@ int kind_of(int scheme)
     case WAVE2D_P9: return KIND9;
     case WAVE2D_C9: return KIND9;
     case WAVE2D_P13: return KIND13;
-    default: return -1;
+    default: {
+        CustomScheme cs;
+        return custom_scheme(scheme, &cs) ? cs.kind : -1;
+    }
     }
 }
 
+// Tuning slot of a scheme; schemes built by wave2d_scheme_create share the
+// slot of the paper's scheme with the same stencil class.
 int scheme_index(int scheme)
 {
     switch (scheme) {
@@ -63,8 +68,21 @@ int scheme_index(int scheme)
     case WAVE2D_P9: return 1;
     case WAVE2D_P13: return 2;
     case WAVE2D_C9: return 3;
-    default: return -1;
+    default: {
+        CustomScheme cs;
+        if (!custom_scheme(scheme, &cs)) return -1;
+        return cs.kind == KIND5 ? 0 : cs.kind == KIND9 ? 1 : 2;
     }
+    }
+}
+
+// Scheme id whose built-in defaults a scheme uses (the paper's scheme of
+// the same stencil class for built schemes).
+int tuning_scheme(int scheme)
+{
+    const int si = scheme_index(scheme);
+    if (si < 0 || scheme < kCustomBase) return scheme;
+    return si == 0 ? WAVE2D_P5 : si == 1 ? WAVE2D_P9 : WAVE2D_P13;
 }
 
 // Node weights of the A and B operators for one neighbour of each class
@@ -99,8 +117,21 @@ bool node_weights(int scheme, double lam, double wa[3], double wb[3], bool* has_
         wb[0] = wb[1] = wb[2] = 0.0;
         *has_b = false;
         return true;
-    default:
-        return false;
+    default: {
+        // Built schemes: the polynomials of the Sec. 4-5 construction.
+        CustomScheme cs;
+        if (!custom_scheme(scheme, &cs)) return false;
+        for (int c = 0; c < 3; ++c) {
+            double sa = 0.0, sb = 0.0;
+            for (int k = CustomScheme::kDeg; k >= 0; --k) {
+                sa = sa * lam + cs.a[c][k];
+                sb = sb * lam + cs.b[c][k];
+            }
+            wa[c] = sa;
+            wb[c] = sb;
+        }
+        return true;
+    }
     }
 }
 
@@ -111,7 +142,10 @@ double lambda_max_of(int scheme)
     case WAVE2D_P9: return std::sqrt((3.0 - std::sqrt(3.0)) * 0.5);
     case WAVE2D_P13: return std::sqrt(0.5);
     case WAVE2D_C9: return std::sqrt(0.75);
-    default: return -1.0;
+    default: {
+        CustomScheme cs;
+        return custom_scheme(scheme, &cs) ? cs.lambda_max : -1.0;
+    }
     }
 }
 
@@ -274,8 +308,9 @@ int device_cus()
 // kernels on 2049^2 to 8193^2 grids); overridable per process.  Without a
 // grid size the height is 8, the least segment height batched launches
 // start from.
-wave2d_tuning default_tuning(int precision, int scheme, int64_t nx, int64_t ny)
+wave2d_tuning default_tuning(int precision, int scheme_in, int64_t nx, int64_t ny)
 {
+    const int scheme = tuning_scheme(scheme_in);
     for (const MeasuredShape& m : kMeasured)
         if (m.precision == precision && m.scheme == scheme && m.nx == nx && m.ny == ny && device_cus() == 256)
             return m.t;
@@ -583,6 +618,11 @@ using namespace w2d_host;
 extern "C" {
 
 double wave2d_lambda_max(int scheme) { return lambda_max_of(scheme); }
+
+int wave2d_scheme_create(int32_t m, const int32_t* nodes, const int32_t* exps, int* scheme)
+{
+    return custom_scheme_create(m, nodes, exps, scheme);
+}
 
 int wave2d_weights(int scheme, uint32_t flags, double lambda, double w2[3], double wa[3], double wb[3])
 {

@@ -29,6 +29,21 @@ struct Params {
     bool has_b;
 };
 
+// A scheme built by wave2d_scheme_create: per class (axis 1, diagonal,
+// axis 2) the node weights of A and of B / tau as polynomials in lambda
+// (coefficient k of lambda^k), the stencil class the kernels run it as,
+// and its stability limit.
+struct CustomScheme {
+    static constexpr int kDeg = 12;
+    double a[3][kDeg + 1];
+    double b[3][kDeg + 1];
+    int kind;
+    double lambda_max;
+};
+constexpr int kCustomBase = 1000;
+int custom_scheme_create(int m, const int32_t* nodes, const int32_t* exps, int* id);
+bool custom_scheme(int id, CustomScheme* out);
+
 int fail(int status, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int kind_of(int scheme);

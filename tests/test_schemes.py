@@ -1,0 +1,182 @@
+"""Schemes built from a stencil and a monomial set (Sec. 4-5), host side.
+
+Pins:
+  * the oracle's construction for explicit sets equals its construction of
+    the paper's sets Q_m, M*_{<=m} (m = 6, 11, 15), which the derivation
+    tests pin to the printed weights;
+  * the oracle's first step and two-step update with the weights of the
+    "cross" set (centre, axis nodes at distance 1 and 2; monomials 1, x^k,
+    y^k, k <= 4) reproduce the exact solution of the wave equation for data
+    in the span of those monomials (interpolation is exact there and the
+    operators A, B are exact on polynomials, Sec. 5);
+  * the library's construction (Taylor series of A and B, floating point)
+    matches the oracle's exact rational one;
+  * the library's numerical stability limit matches the paper's limits on
+    the paper's sets, the closed form sqrt(2 - sqrt(5/2)) of the (pi, pi)
+    mode for the cross set, and brute-force stepping by the oracle (bounded
+    at 0.99 of the limit, blow-up at 1.01 on a periodic grid).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1904_04048_amd as w
+from oracle import derive
+from paper_1904_04048_amd._lib import EINVAL
+
+C0 = [(0, 0)]
+AX1 = [(1, 0), (-1, 0), (0, 1), (0, -1)]
+DG = [(1, 1), (-1, 1), (-1, -1), (1, -1)]
+AX2 = [(2, 0), (-2, 0), (0, 2), (0, -2)]
+CROSS_NODES = C0 + AX1 + AX2
+CROSS_EXPS = [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (3, 0), (0, 3), (4, 0), (0, 4)]
+ORC_CROSS = 1000
+
+
+@pytest.fixture(scope="module")
+def cross_oracle():
+    wts = derive.node_weights_for(CROSS_NODES, CROSS_EXPS)
+    oracle.register_scheme(ORC_CROSS, wts)
+    return wts
+
+
+def test_oracle_generic_construction_equals_paper_sets():
+    for m in (6, 11, 15):
+        assert derive.node_weights_for(derive.stencil(m), derive.monomials(m)) == derive.node_weights(m)
+
+
+def test_oracle_cross_weights_are_symmetric_and_reproduce_constants(cross_oracle):
+    from fractions import Fraction
+    A0, B0 = cross_oracle[(1, 0)]
+    for q in AX1:
+        assert cross_oracle[q] == (A0, B0)
+    for q in AX2[1:]:
+        assert cross_oracle[q] == cross_oracle[AX2[0]]
+    for k in range(0, 7):
+        sa = sum(A.get(k, Fraction(0)) for A, _ in cross_oracle.values())
+        sb = sum(B.get(k, Fraction(0)) for _, B in cross_oracle.values())
+        assert sa == (1 if k == 0 else 0) and sb == (1 if k == 0 else 0)
+
+
+def _exact_cross(X, Y, t, c):
+    # u0 = x^4 + y^3, v0 = x^3 + 1: u(t) = A(t) u0 + B(t) v0 with
+    # A f = sum (ct)^{2j}/(2j)! Lap^j f, B f = sum t^{2j+1} c^{2j}/(2j+1)! Lap^j f.
+    A = X**4 + 6 * (c * t) ** 2 * X**2 + (c * t) ** 4 + Y**3 + 3 * (c * t) ** 2 * Y
+    B = t * (X**3 + 1) + t**3 * c**2 * X
+    return A + B
+
+
+def test_oracle_cross_scheme_is_exact_on_its_polynomials(cross_oracle):
+    n = 41
+    h = 0.05
+    c = 1.3
+    lam = 0.5
+    tau = lam * h / c
+    x = (np.arange(n) - n // 2) * h
+    X, Y = np.meshgrid(x, x)
+    u0 = X**4 + Y**3
+    v0 = X**3 + 1.0
+    up, uc = oracle.run(u0, v0, h, tau, c, ORC_CROSS, 4)
+    for k, got in ((3, up), (4, uc)):
+        ref = _exact_cross(X, Y, k * tau, c)
+        far = slice(2 + 2 * k + 1, n - 2 - 2 * k - 1)
+        err = np.max(np.abs(got[far, far] - ref[far, far])) / np.max(np.abs(ref[far, far]))
+        assert err < 1e-12, (k, err)
+
+
+@pytest.mark.parametrize("m,ref", [(6, w.P5), (11, w.P9), (15, w.P13)])
+def test_library_construction_of_paper_sets(m, ref):
+    sid = w.wave2d_scheme_create(derive.stencil(m), derive.monomials(m))
+    assert sid >= 1000
+    assert abs(w.wave2d_lambda_max(sid) / oracle.lambda_max(ref) - 1) < 1e-9
+    exact = derive.node_weights(m)
+    for lam in (0.05, 0.3, 0.55, 0.7):
+        _, wa, wb = w.wave2d_weights(sid, lam)
+        for c, q in enumerate([(1, 0), (1, 1), (2, 0)]):
+            A, B = exact.get(q, ({}, {}))
+            assert abs(wa[c] - derive.evaluate(A, lam)) < 1e-14
+            assert abs(wb[c] - derive.evaluate(B, lam)) < 1e-14
+
+
+def test_library_cross_scheme(cross_oracle):
+    sid = w.wave2d_scheme_create(CROSS_NODES, CROSS_EXPS)
+    lmax = w.wave2d_lambda_max(sid)
+    # (pi, pi) mode: -8 * 2 A_10 = -4  <=>  lambda^4 - 4 lambda^2 + 3/2 = 0
+    assert abs(lmax - math.sqrt(2.0 - math.sqrt(2.5))) < 1e-10
+    for lam in (0.1, 0.4, 0.64):
+        w2, wa, wb = w.wave2d_weights(sid, lam)
+        for c, q in enumerate([(1, 0), (1, 1), (2, 0)]):
+            A, B = cross_oracle.get(q, ({}, {}))
+            assert abs(wa[c] - derive.evaluate(A, lam)) < 1e-14
+            assert abs(wb[c] - derive.evaluate(B, lam)) < 1e-14
+            assert w2[c] == 2 * wa[c]
+    # the conventional first step drops the B stencil
+    _, _, wb = w.wave2d_weights(sid, 0.4, w.FIRST_CONVENTIONAL)
+    assert wb == [0.0, 0.0, 0.0]
+
+
+def _growth(scheme, lam, n=32, steps=3000, seed=3):
+    rng = np.random.default_rng(seed)
+    u0 = rng.standard_normal((n, n))
+    v0 = np.zeros((n, n))
+    h = 1.0 / n
+    _, u = oracle.run(u0, v0, h, lam * h, 1.0, scheme, steps, oracle.PERIODIC)
+    return np.max(np.abs(u)) / np.max(np.abs(u0))
+
+
+def test_library_limit_against_brute_force_stepping(cross_oracle):
+    sid = w.wave2d_scheme_create(CROSS_NODES, CROSS_EXPS)
+    lmax = w.wave2d_lambda_max(sid)
+    assert _growth(ORC_CROSS, 0.99 * lmax) < 10.0
+    g = _growth(ORC_CROSS, 1.01 * lmax)
+    assert not np.isfinite(g) or g > 1e3
+
+
+@pytest.mark.parametrize("nodes,exps,msg", [
+    (C0 + AX1, [(0, 0), (1, 0), (0, 1), (2, 0), (3, 0)], "not unisolvent"),
+    (C0 + AX1[:3] + [(1, 1)], [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1)], "symmetric"),
+    (C0 + AX1 + [(2, 1), (-2, 1), (-2, -1), (2, -1), (1, 2), (-1, 2), (-1, -2), (1, -2)],
+     [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (0, 3), (0, 4), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (3, 0)],
+     "outside the 13-point classes"),
+    (AX1 + AX2 + [(1, 1)], [(1, 0), (0, 1), (2, 0), (0, 2), (3, 0), (0, 3), (4, 0), (0, 4), (2, 2)], "constants"),
+    (C0 + C0, [(0, 0), (1, 0)], "appears twice"),
+    (C0 + [(9, 0)], [(0, 0), (1, 0)], "more than 8"),
+])
+def test_scheme_create_rejects(nodes, exps, msg):
+    with pytest.raises(w.Wave2dError) as e:
+        w.wave2d_scheme_create(nodes, exps)
+    assert e.value.status == EINVAL and msg in str(e.value), str(e.value)
+
+
+def test_scheme_create_rejects_empty():
+    with pytest.raises(w.Wave2dError):
+        w.wave2d_scheme_create([], [])
+
+
+def test_built_scheme_in_validation():
+    # An id that was never created is unknown; a created one is accepted by
+    # the host checks of every call and keeps its stability limit.
+    with pytest.raises(ValueError):
+        w.wave2d_lambda_max(1999)
+    sid = w.wave2d_scheme_create(CROSS_NODES, CROSS_EXPS)
+    with pytest.raises(w.Wave2dError) as e:
+        w.wave2d_weights(1999, 0.5)
+    assert e.value.status == EINVAL
+    assert w.wave2d_get_tuning(w.F32C, sid, 0, 0)[0] in (1, 2, 3, 4, 6, 8)
+
+
+@pytest.mark.parametrize("nodes,exps,ref", [
+    ([(i, j) for j in (-1, 0, 1) for i in (-1, 0, 1)], [(a, b) for b in (0, 1, 2) for a in (0, 1, 2)], w.P9),
+    (C0 + AX1 + DG + AX2, [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1), (1, 2), (0, 3),
+                           (4, 0), (2, 2), (0, 4)], w.P13),
+], ids=["tensor3x3", "deg3-plus-quartics"])
+def test_other_sets_with_the_same_even_part_give_the_paper_schemes(nodes, exps, ref):
+    # A and B see only the even monomials, so sets whose even monomials are
+    # those of the paper's sets give the paper's weights.
+    sid = w.wave2d_scheme_create(nodes, exps)
+    assert abs(w.wave2d_lambda_max(sid) / w.wave2d_lambda_max(ref) - 1) < 1e-9
+    for lam in (0.2, 0.5, 0.7):
+        for x, y in zip(w.wave2d_weights(sid, lam), w.wave2d_weights(ref, lam)):
+            assert np.allclose(x, y, rtol=0, atol=1e-14)
