@@ -200,7 +200,10 @@ bool stream_ok(const Grid& g, size_t elt)
     return (g.nx % 2 == 0) && (uint64_t)g.ld * (uint64_t)g.ny * elt < (uint64_t(1) << 31);
 }
 
-StepW64 step_w64(const Params& p) { return StepW64{2.0 * p.wa[0], 2.0 * p.wa[1], 2.0 * p.wa[2]}; }
+StepW64 step_w64(const Params& p)
+{
+    return StepW64{2.0 * p.wa[0], 2.0 * p.wa[1], 2.0 * p.wa[2], 2.0 * p.wa[0] + 4.0 * p.wa[1] + 8.0 * p.wa[2]};
+}
 
 StepW32 step_w32(const Params& p)
 {
@@ -292,6 +295,9 @@ const MeasuredShape kMeasured[] = {
     {WAVE2D_F32C, WAVE2D_P5, 4097, 4097, {8, 40}},   // 890
     {WAVE2D_F32C, WAVE2D_P13, 4097, 4097, {6, 44}},  // 560
     {WAVE2D_F32C, WAVE2D_P13, 8193, 8193, {6, 112}}, // 778
+    {WAVE2D_F64, WAVE2D_P9, 4097, 4097, {8, 40}},    // 821
+    {WAVE2D_F64, WAVE2D_P5, 4097, 4097, {8, 40}},    // 864
+    {WAVE2D_F64, WAVE2D_P13, 4097, 4097, {4, 48}},   // 416
 };
 
 int device_cus()
@@ -316,7 +322,7 @@ wave2d_tuning default_tuning(int precision, int scheme_in, int64_t nx, int64_t n
             return m.t;
     int depth;
     if (precision == WAVE2D_F32C) depth = (scheme == WAVE2D_P13) ? 6 : 8;
-    else depth = (scheme == WAVE2D_P13) ? 3 : 6;
+    else depth = (scheme == WAVE2D_P13) ? 4 : 8;
     const int rows = (nx > 0 && ny > 0) ? fill_rows(precision, kind_of(scheme), depth, nx, ny) : 8;
     return wave2d_tuning{depth, rows};
 }

@@ -106,6 +106,24 @@ __device__ __forceinline__ float f32c_incr(const Nbh<float>& u, const Nbh<float>
     }
 }
 
+// The same increment in double precision on one field (the FP64 two-step
+// update): the 5-point scheme as lap_diff, the 9- and 13-point schemes
+// regrouped as f32c_incr without the lo terms.
+template <int K>
+__device__ __forceinline__ double f64_incr(const Nbh<double>& u, double w10, double w11, double w20, double wx)
+{
+    if constexpr (K == KIND5) {
+        return lap_diff<K>(u, w10, w11, w20);
+    } else {
+        const double q = d2(u.N, u.C, u.S);
+        const double p = d2(u.E, u.C, u.W);
+        double s = fmaT(w11, d2(d2(u.NE, u.E, u.SE), q, d2(u.NW, u.W, u.SW)), wx * (p + q));
+        if constexpr (KT<K>::AX2)
+            s = fmaT(w20, d2(d2(u.EE, u.E, u.C), p, d2(u.C, u.W, u.WW)) + d2(d2(u.NN, u.N, u.C), q, d2(u.C, u.S, u.SS)), s);
+        return s;
+    }
+}
+
 // FP64 two-step update (Sec. 3, eq. A2): u^{k+1} = 2u^k - u^{k-1} + s.
 __device__ __forceinline__ double f64_update(double C, double P, double s) { return ((C + C) - P) + s; }
 

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_f64(Grid g, StepW64 w, const do
     double r = 0.0;
     if (interior(g, i, j)) {
         const Nbh<double> v = gather<K>(u_cur, g, i, j);
-        r = f64_update(v.C, u_prev[(size_t)j * g.ld + i], lap_diff<K>(v, w.w10, w.w11, w.w20));
+        r = f64_update(v.C, u_prev[(size_t)j * g.ld + i], f64_incr<K>(v, w.w10, w.w11, w.w20, w.wx));
     }
     u_next[(size_t)j * g.ld + i] = r;
 }

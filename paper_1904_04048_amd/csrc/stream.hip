@@ -135,51 +135,6 @@ __device__ __forceinline__ void buf_store1(T x, __amdgpu_buffer_rsrc_t r, uint32
     }
 }
 
-// Double-precision stencil update of one row segment (CW columns per lane)
-// of level t from the level t-1 window rows (centre, north, south, and the
-// second ring for the 13-point stencil), extended by R columns on each
-// side, and the level t-1 point field.
-template <class Prec, int K, int CW>
-__device__ __forceinline__ void row_update(
-    const typename Prec::T (&Wc)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Wn)[Prec::NW][CW + 2 * KT<K>::R],
-    const typename Prec::T (&Ws)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Wnn)[Prec::NW][CW + 2 * KT<K>::R],
-    const typename Prec::T (&Wss)[Prec::NW][CW + 2 * KT<K>::R], const typename Prec::T (&Pin)[CW],
-    const typename Prec::W& w, typename Prec::T (&nv)[Prec::NW][CW + 2 * KT<K>::R], typename Prec::T (&np)[CW])
-{
-    using T = typename Prec::T;
-    constexpr int R = KT<K>::R;
-    static_assert(Prec::NW == 1, "extended rows are used by the double-precision path only");
-#pragma unroll
-    for (int m = 0; m < CW; ++m) {
-        const int e = R + m;
-        Nbh<T> nb;
-        nb.C = Wc[0][e];
-        nb.E = Wc[0][e + 1];
-        nb.W = Wc[0][e - 1];
-        nb.N = Wn[0][e];
-        nb.S = Ws[0][e];
-        if constexpr (KT<K>::DIAG) {
-            nb.NE = Wn[0][e + 1];
-            nb.NW = Wn[0][e - 1];
-            nb.SE = Ws[0][e + 1];
-            nb.SW = Ws[0][e - 1];
-        } else {
-            nb.NE = nb.NW = nb.SE = nb.SW = T(0);
-        }
-        if constexpr (KT<K>::AX2) {
-            nb.EE = Wc[0][e + 2];
-            nb.WW = Wc[0][e - 2];
-            nb.NN = Wnn[0][e];
-            nb.SS = Wss[0][e];
-        } else {
-            nb.EE = nb.WW = nb.NN = nb.SS = T(0);
-        }
-        const T s = lap_diff<K>(nb, w.w10, w.w11, w.w20);
-        nv[0][e] = (T)f64_update((double)nb.C, (double)Pin[m], (double)s);
-        np[m] = nb.C;
-    }
-}
-
 // Compensated single precision with differences carried from row to row:
 // going down the rows of one level, what row y-1 computed for its northern
 // neighbours serves row y as its southern ones.  Every operation and its
@@ -193,26 +148,26 @@ __device__ __forceinline__ void row_update(
 //            q = Dy u + Dy lo of row y and q(y) - q(y-1).
 // Column neighbours beyond the lane's own CW columns come from the adjacent
 // lanes (DPP shifts folded into the consuming subtraction or addition).
-template <int CW>
+template <typename T, int CW>
 struct Carry {
-    float dv[CW];  // N - C of u
-    float dl[CW];  // N - C of lo (9-, 13-point)
-    float hs0[CW]; // lo(i+1) + lo(i-1) of row y-1 (5-point)
-    float hs1[CW]; // lo(i+1) + lo(i-1) of row y (5-point)
-    float q[CW];   // q of row y (13-point)
-    float eq[CW];  // q(y) - q(y-1) (13-point)
+    T dv[CW];  // N - C of u
+    T dl[CW];  // N - C of lo (9-, 13-point)
+    T hs0[CW]; // lo(i+1) + lo(i-1) of row y-1 (5-point)
+    T hs1[CW]; // lo(i+1) + lo(i-1) of row y (5-point)
+    T q[CW];   // q of row y (13-point)
+    T eq[CW];  // q(y) - q(y-1) (13-point)
 };
 
-template <int CW>
-__device__ __forceinline__ void carry_zero(Carry<CW>& c)
+template <typename T, int CW>
+__device__ __forceinline__ void carry_zero(Carry<T, CW>& c)
 {
 #pragma unroll
-    for (int m = 0; m < CW; ++m) c.dv[m] = c.dl[m] = c.hs0[m] = c.hs1[m] = c.q[m] = c.eq[m] = 0.f;
+    for (int m = 0; m < CW; ++m) c.dv[m] = c.dl[m] = c.hs0[m] = c.hs1[m] = c.q[m] = c.eq[m] = T(0);
 }
 
 // column m + o of a lane's row, o in [-1, 1]
-template <int CW>
-__device__ __forceinline__ float lane_col(const float (&r)[CW], int m, int o)
+template <typename T, int CW>
+__device__ __forceinline__ T lane_col(const T (&r)[CW], int m, int o)
 {
     const int c = m + o;
     if (c >= 0 && c < CW) return r[c];
@@ -222,10 +177,10 @@ __device__ __forceinline__ float lane_col(const float (&r)[CW], int m, int o)
 
 // Second difference along x of a lane's row: out[m] = d2(r(m+1), r(m), r(m-1)),
 // from the first differences e[k] = r(k) - r(k-1), k = 0..CW.
-template <int CW>
-__device__ __forceinline__ void row_d2x(const float (&r)[CW], float (&out)[CW])
+template <typename T, int CW>
+__device__ __forceinline__ void row_d2x(const T (&r)[CW], T (&out)[CW])
 {
-    float e[CW + 1];
+    T e[CW + 1];
     e[0] = r[0] - from_left(r[CW - 1]);
 #pragma unroll
     for (int k = 1; k < CW; ++k) e[k] = r[k] - r[k - 1];
@@ -237,8 +192,9 @@ __device__ __forceinline__ void row_d2x(const float (&r)[CW], float (&out)[CW])
 template <int K, int CW>
 __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const float (&Wn)[2][CW],
                                                  const float (&Ws)[2][CW], const float (&Wnn)[2][CW],
-                                                 const float (&Wss)[2][CW], const float (&Pin)[CW], Carry<CW>& cr,
-                                                 const StepW32& w, bool update, float (&nv)[2][CW], float (&np)[CW])
+                                                 const float (&Wss)[2][CW], const float (&Pin)[CW],
+                                                 Carry<float, CW>& cr, const StepW32& w, bool update,
+                                                 float (&nv)[2][CW], float (&np)[CW])
 {
     const float(&U)[CW] = Wc[0];
     const float(&L)[CW] = Wc[1];
@@ -328,17 +284,85 @@ __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const
     }
 }
 
-// Fill the R neighbour columns on each side of an extended row from the
-// adjacent lanes.
-template <typename T, int NW, int CW, int R>
-__device__ __forceinline__ void extend_row(T (&v)[NW][CW + 2 * R])
+// The double-precision two-step update (one field u; the point field holds
+// the previous level) with the same carried differences: f64_incr row by
+// row, bit-identical to the one-node-per-thread kernel.  Neighbour columns
+// beyond the lane's pair come from the adjacent lanes (two 32-bit DPP moves
+// per value).
+template <int K, int CW>
+__device__ __forceinline__ void row_update_carry(const double (&Wc)[1][CW], const double (&Wn)[1][CW],
+                                                 const double (&Ws)[1][CW], const double (&Wnn)[1][CW],
+                                                 const double (&Wss)[1][CW], const double (&Pin)[CW],
+                                                 double (&cdv)[CW], double (&cq)[CW], double (&ceq)[CW],
+                                                 const StepW64& w, bool update, double (&nv)[1][CW],
+                                                 double (&np)[CW])
 {
+    const double(&U)[CW] = Wc[0];
+    if constexpr (K == KIND5) {
+        double dv[CW];
 #pragma unroll
-    for (int f = 0; f < NW; ++f) {
+        for (int m = 0; m < CW; ++m) dv[m] = Wn[0][m] - U[m];
+        if (update) {
+            double eh[CW + 1];
+            eh[0] = U[0] - from_left(U[CW - 1]);
 #pragma unroll
-        for (int e = 0; e < R; ++e) v[f][e] = from_left(v[f][CW + e]);
+            for (int k = 1; k < CW; ++k) eh[k] = U[k] - U[k - 1];
+            eh[CW] = from_right(U[0]) - U[CW - 1];
 #pragma unroll
-        for (int e = R + CW; e < CW + 2 * R; ++e) v[f][e] = from_right(v[f][e - CW]);
+            for (int m = 0; m < CW; ++m) {
+                const double s = w.w10 * ((eh[m + 1] - eh[m]) + (dv[m] - cdv[m]));
+                nv[0][m] = f64_update(U[m], Pin[m], s);
+                np[m] = U[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) cdv[m] = dv[m];
+    } else if constexpr (K == KIND9) {
+        double dv[CW];
+#pragma unroll
+        for (int m = 0; m < CW; ++m) dv[m] = Wn[0][m] - U[m];
+        if (update) {
+            double q[CW], xu[CW], xq[CW];
+#pragma unroll
+            for (int m = 0; m < CW; ++m) q[m] = dv[m] - cdv[m];
+            row_d2x(U, xu);
+            row_d2x(q, xq);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const double s = fmaT(w.w11, xq[m], w.wx * (xu[m] + q[m]));
+                nv[0][m] = f64_update(U[m], Pin[m], s);
+                np[m] = U[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) cdv[m] = dv[m];
+    } else {
+        double dv[CW], qn[CW];
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            dv[m] = Wnn[0][m] - Wn[0][m];
+            qn[m] = dv[m] - cdv[m];
+        }
+        if (update) {
+            double p[CW], xq[CW], xp[CW];
+            row_d2x(U, p);
+            row_d2x(cq, xq);
+            row_d2x(p, xp);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const double q = cq[m];
+                double s = fmaT(w.w11, xq[m], w.wx * (p[m] + q));
+                s = fmaT(w.w20, xp[m] + ((qn[m] - q) - ceq[m]), s);
+                nv[0][m] = f64_update(U[m], Pin[m], s);
+                np[m] = U[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            cdv[m] = dv[m];
+            ceq[m] = qn[m] - cq[m];
+            cq[m] = qn[m];
+        }
     }
 }
 
@@ -447,12 +471,9 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     constexpr int H = R * DEPTH;   // rows / columns a pass reaches beyond its outputs
     constexpr int HP = halo_cols<R, DEPTH>();
     constexpr int SW = kWave * CW - 2 * HP;
-    // Single precision keeps only the lane's own columns per row and
-    // fetches neighbours where they are used; double precision cannot fold
-    // the shifts into its arithmetic and keeps extended rows instead.
-    constexpr bool EXT = (Prec::NW == 1);
-    constexpr int E = EXT ? CW + 2 * R : CW;
-    constexpr int CB = EXT ? R : 0;  // index of the lane's first column in a row
+    // Rows hold only the lane's own columns; neighbours beyond them are
+    // fetched from the adjacent lanes where they are used.
+    constexpr int E = CW;
     static_assert(CW == 2, "reflected loads assume column pairs");
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -584,12 +605,11 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
         int jr = jj;
         if constexpr (BND) (void)map_node(jj, ny, per, jr);
         const uint32_t so = (uint32_t)((jr - base_row) * row_bytes);
-        constexpr int off = (sizeof(v[0]) / sizeof(T) == E) ? CB : 0;  // window rows carry the extension
 #pragma unroll
         for (int f = 0; f < NW; ++f) {
             const Vec<T, CW> x = buf_load<T, CW>(rs_in[f], voff, so);
 #pragma unroll
-            for (int m = 0; m < CW; ++m) v[f][off + m] = x.v[m];
+            for (int m = 0; m < CW; ++m) v[f][m] = x.v[m];
         }
         int jp = point_row(jj);
         if constexpr (DEPTH == 1) {
@@ -601,14 +621,19 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
         for (int m = 0; m < CW; ++m) p[m] = x.v[m];
     };
 
-    // Differences carried down the rows of each level (single precision).
-    // They are refreshed at every row of every level, also where a level's
-    // update is skipped during the warm-up, so the first updated row of a
-    // level finds the previous row's values.
-    Carry<CW> carry[EXT ? 1 : DEPTH];
-    if constexpr (!EXT) {
+    // Differences carried down the rows of each level.  They are refreshed
+    // at every row of every level, also where a level's update is skipped
+    // during the warm-up, so the first updated row of a level finds the
+    // previous row's values.
+    // Single precision: Carry structs.  Double precision: plain arrays (the
+    // compiler keeps a struct of double arrays in scratch memory).
+    Carry<float, CW> carry[NW > 1 ? DEPTH : 1];
+    T cdv[DEPTH][CW], cq[DEPTH][CW], ceq[DEPTH][CW];
 #pragma unroll
-        for (int t = 0; t < DEPTH; ++t) carry_zero(carry[t]);
+    for (int t = 0; t < DEPTH; ++t) {
+        if constexpr (NW > 1) carry_zero(carry[t]);
+#pragma unroll
+        for (int m = 0; m < CW; ++m) cdv[t][m] = cq[t][m] = ceq[t][m] = T(0);
     }
 
     auto phase = [&](int ph, int j, bool warm) {
@@ -618,13 +643,12 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
                 int jr;
                 const int sy = reflect(j, ny, jr);
 #pragma unroll
-                for (int f = 0; f < NW; ++f) reflect_vals(win[0][ph][f][CB], win[0][ph][f][CB + 1], sy);
+                for (int f = 0; f < NW; ++f) reflect_vals(win[0][ph][f][0], win[0][ph][f][1], sy);
                 const int sp = reflect(point_row(j), ny, jr);
                 T(&p)[CW] = pf[0][mod_c(ph - R, NS)];
                 reflect_vals(p[0], p[1], sp);
             }
         }
-        if constexpr (EXT) extend_row<T, NW, CW, R>(win[0][ph]);
         // Levels 1..DEPTH at rows j - t*R; the next row enters the window
         // right after level 1, whose inputs it overwrites.
 #pragma unroll
@@ -636,7 +660,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
 #pragma unroll
                     for (int f = 0; f < NW; ++f)
 #pragma unroll
-                        for (int m = 0; m < CW; ++m) dv[f][CB + m] = stg[mod_c(ph + 1, NS)][f][m];
+                        for (int m = 0; m < CW; ++m) dv[f][m] = stg[mod_c(ph + 1, NS)][f][m];
 #pragma unroll
                     for (int m = 0; m < CW; ++m) dp[m] = stp[mod_c(ph + 1, NS)][m];
                     issue_loads(j + PF, stg[mod_c(ph + PF, NS)], stp[mod_c(ph + PF, NS)]);
@@ -645,24 +669,27 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
                 }
             }
             const int y = j - t * R;
-            const bool skip = warm && y < y0 - (DEPTH - t) * R;
+            // Warm-up rows below a level's first needed row are skipped in
+            // single precision.  Double precision computes them (they lie
+            // outside the outputs' dependency cone): the branch lets the
+            // compiler merge stores to different private arrays, which then
+            // stay in scratch memory.
+            const bool skip = (NW > 1) && warm && y < y0 - (DEPTH - t) * R;
             const int sy = mod_c(ph - t * R, NS);
             T nv[NW][E];
             T np[CW];
-            if constexpr (EXT) {
-                if (skip) continue;
-                row_update<Prec, K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
-                                        win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
-                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], w, nv, np);
-            } else {
+            if constexpr (NW > 1)
                 row_update_carry<K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
                                         win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
                                         win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], carry[t - 1], w, !skip,
                                         nv, np);
-                if (skip) continue;
-            }
+            else
+                row_update_carry<K, CW>(win[t - 1][sy], win[t - 1][mod_c(ph - t * R + 1, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 1, NS)], win[t - 1][mod_c(ph - t * R + 2, NS)],
+                                        win[t - 1][mod_c(ph - t * R - 2, NS)], pf[t - 1][sy], cdv[t - 1], cq[t - 1],
+                                        ceq[t - 1], w, !skip, nv, np);
+            if (skip) continue;
             if (t < DEPTH) {
-                if constexpr (EXT) extend_row<T, NW, CW, R>(nv);
                 T(&dst)[NW][E] = win[t][sy];
 #pragma unroll
                 for (int f = 0; f < NW; ++f)
@@ -677,7 +704,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
                     for (int f = 0; f < NW; ++f) {
                         Vec<T, CW> x;
 #pragma unroll
-                        for (int m = 0; m < CW; ++m) x.v[m] = nv[f][CB + m];
+                        for (int m = 0; m < CW; ++m) x.v[m] = nv[f][m];
                         buf_store<T, CW>(x, rs_out[f], voff_st, so);
                     }
                     if (a.out_p) {
@@ -689,7 +716,7 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
                 } else {
                     // Last lane of the grid: its first column only (xl = nx - 1).
 #pragma unroll
-                    for (int f = 0; f < NW; ++f) buf_store1<T>(nv[f][CB], rs_out[f], voff_st, so);
+                    for (int f = 0; f < NW; ++f) buf_store1<T>(nv[f][0], rs_out[f], voff_st, so);
                     if (a.out_p) buf_store1<T>(np[0], rs_pout, voff_st, so);
                 }
             }

@@ -17,7 +17,7 @@ struct Grid {
 
 // Two-step weights (2 x the A-operator node weights).
 struct StepW64 {
-    double w10, w11, w20;
+    double w10, w11, w20, wx;  // wx = w10 + 2 w11 + 4 w20
 };
 // wc = -4 (w10 + w11 + w20) (centre weight), wx = w10 + 2 w11 + 4 w20 (the
 // weight of Dx + Dy in the regrouped 9- and 13-point increments).
