@@ -252,6 +252,58 @@ def summarize(prof_dir):
     print(open(VALU_MD).read())
 
 
+def other_workloads():
+    """Throughput of the two other single-grid workloads (not the headline):
+    the 5-point FP64 standing wave on 257^2 (400 levels, launch-latency
+    bound) and the 13-point Gaussian pulse on 8193^2 (3000 levels,
+    compensated, with its error against the FP64 GPU solve)."""
+    import torch
+
+    import paper_1904_04048_amd as w
+    from paper_1904_04048_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def timed(f, reps):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
+
+    p = W.c1()
+    u0, v0 = p.data()
+    U0, V0 = torch.from_numpy(u0).to(dev), torch.from_numpy(v0).to(dev)
+    P, C = torch.empty_like(U0), torch.empty_like(U0)
+    t = timed(lambda: w.wave2d_run(U0, V0, P, C, p.h, p.tau, p.c, p.scheme, p.steps), 5)
+    out["standing_wave_257_fp64"] = {"workload": "5-point, 257x257, 400 levels, FP64, u0 = sin pi x sin pi y",
+                                     "ms_per_solve": round(t * 1e3, 3), "value": round(p.lup / t / 1e9, 2),
+                                     "unit": "GLUP/s"}
+    p = W.c3()
+    u0, v0 = p.data()
+    U0, V0 = torch.from_numpy(u0).to(dev), torch.from_numpy(v0).to(dev)
+    u = torch.empty((p.ny, p.nx), dtype=torch.float32, device=dev)
+    lo, d = torch.empty_like(u), torch.empty_like(u)
+    t = timed(lambda: w.wave2d_f32c_run(U0, V0, u, lo, d, p.h, p.tau, p.c, p.scheme, p.steps), 2)
+    P, C = torch.empty_like(U0), torch.empty_like(U0)
+    t64 = timed(lambda: w.wave2d_run(U0, V0, P, C, p.h, p.tau, p.c, p.scheme, p.steps), 1)
+    nr = w.wave2d_f32c_norms(u, lo, C)
+    depth, rows = w.wave2d_get_tuning(w.F32C, p.scheme, p.nx, p.ny)
+    out["gaussian_8193_13pt"] = {"workload": "13-point, 8193x8193, 3000 levels, Gaussian pulse, compensated FP32",
+                                 "ms_per_solve": round(t * 1e3, 2), "value": round(p.lup / t / 1e9, 2),
+                                 "unit": "GLUP/s", "depth": depth, "rows": rows,
+                                 "fp64_value": round(p.lup / t64 / 1e9, 2),
+                                 "max_rel_err_vs_gpu_fp64": nr[0] / nr[1]}
+    del U0, V0, u, lo, d, P, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_bench(args):
     """The batched workload: 512 seeded instances (sides log-uniform in
     [64, 2048], schemes uniform over 5/9/13-point, lambda in [0.3, 0.9] x
@@ -508,9 +560,10 @@ def main():
                       "depth": w.wave2d_get_tuning(w.F64, p.scheme, p.nx, p.ny)[0]},
         "roofline": roofline,
     }
+    del u, lo, d, work, work64, UP, UC, U_ex
+    torch.cuda.empty_cache()
+    out["other_workloads"] = other_workloads()
     if not args.no_batch:
-        del u, lo, d, work, work64, UP, UC, U_ex
-        torch.cuda.empty_cache()
         out["batch"] = batch_bench(args)
         torch.cuda.empty_cache()
     if not args.no_serve:
