@@ -36,7 +36,7 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # s = su + slo and the 6-operation TwoSum = 9.
 FLOPS_PER_LUP_F32C_9PT = 37
 STATE_BYTES_PER_NODE = 24  # compensated state (u, lo, d): 12 B read + 12 B written per node per pass
-KERNEL_NAME = "k_stream_interior+k_stream_general<PF32C,KIND9> (one pass)"
+KERNEL_NAME = "k_stream_fused<PF32C,KIND9> (one pass: boundary and interior work items)"
 
 
 def parse():
@@ -147,7 +147,7 @@ def summarize(prof_dir):
     per = {}
     for r in csv.DictReader(open(os.path.join(prof_dir, "prof_bench", "bench_kernel_trace.csv"))):
         n = r["Kernel_Name"]
-        for kind in ("interior", "general"):
+        for kind in ("fused",):
             if f"k_stream_{kind}<" in n and f"PF32C, 1, {depth}, 2>" in n:
                 dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
                 per.setdefault(kind, {}).setdefault(int(r["Grid_Size_X"]), []).append(dur)
@@ -158,8 +158,7 @@ def summarize(prof_dir):
         v = by_grid[g]
         lines.append(f"| k_stream_{kind}<PF32C,KIND9,{depth}> | {g // 64} | {len(v)} | {sum(v)/len(v):.1f} | "
                      f"{min(v):.1f} | {max(v):.1f} |")
-    lines += ["", "The boundary kernel runs on a side stream beside the interior kernel; one pass takes about the "
-              "interior kernel's time.", ""]
+    lines += ["", "One launch per pass holds the boundary work items (first wave ids) and the interior ones.", ""]
     open(STATS_MD, "w").write("\n".join(lines) + "\n")
 
     def per_kernel(path):
@@ -176,11 +175,11 @@ def summarize(prof_dir):
     w_scale = copy_bytes / (statistics.median(cw) * 1024)
     from paper_1904_04048_amd import workloads as W
     p = W.c2()
-    # One pass = the boundary-strip kernel and the interior kernel of this depth.
+    # One pass = one launch of the fused kernel of this depth.
     tag = f"PF32C, 1, {depth}, 2>"
-    kf = [statistics.median(v) for k, v in fetch.items() if "k_stream_" in k and tag in k]
-    kw = [statistics.median(v) for k, v in write.items() if "k_stream_" in k and tag in k]
-    assert len(kf) == 2 and len(kw) == 2, (len(kf), len(kw))
+    kf = [statistics.median(v) for k, v in fetch.items() if "k_stream_fused" in k and tag in k]
+    kw = [statistics.median(v) for k, v in write.items() if "k_stream_fused" in k and tag in k]
+    assert len(kf) == 1 and len(kw) == 1, (len(kf), len(kw))
     rd = sum(kf) * 1024 * f_scale
     wr = sum(kw) * 1024 * w_scale
     assert cfg["source"] == kernel_source_hash(), "profiles were taken on other kernel sources"
@@ -195,7 +194,7 @@ def summarize(prof_dir):
           "    python3 bench.py --mode summarize", "",
           f"Copy calibration (256 MiB device copy): FETCH_SIZE reads {statistics.median(cf):.0f} KiB "
           f"(scale {f_scale:.3f}), WRITE_SIZE reads {statistics.median(cw):.0f} KiB (scale {w_scale:.3f}).", "",
-          f"One pass of the step kernels (boundary + interior), depth {depth}, rows {rows}: FETCH_SIZE "
+          f"One pass of the step kernel (boundary and interior items), depth {depth}, rows {rows}: FETCH_SIZE "
           f"{sum(kf):.0f} KiB, WRITE_SIZE {sum(kw):.0f} KiB per pass; scaled: read {rd/1e6:.1f} MB, "
           f"write {wr/1e6:.1f} MB per launch against {alg/1e6:.1f} MB algorithmic "
           f"({(rd + wr)/alg:.2f}x).", "", "```json", json.dumps(rec, indent=1), "```", ""]
@@ -211,16 +210,15 @@ def summarize(prof_dir):
     def per_kernel_counter(path):
         out = {}
         for r in csv.DictReader(open(path)):
-            if "k_stream_" in r["Kernel_Name"] and tag in r["Kernel_Name"]:
-                kind = "interior" if "k_stream_interior" in r["Kernel_Name"] else "boundary"
-                out.setdefault((kind, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+            if "k_stream_fused" in r["Kernel_Name"] and tag in r["Kernel_Name"]:
+                out.setdefault(("pass", r["Counter_Name"]), []).append(float(r["Counter_Value"]))
         return {k: statistics.median(v) for k, v in out.items()}
     sq = per_kernel_counter(sq_csv)
     sq.update(per_kernel_counter(gr_csv))
     simds = 256 * 4
     lup = p.interior * depth
     rows_md = []
-    for kind in ("interior", "boundary"):
+    for kind in ("pass",):
         v = {c: sq.get((kind, c)) for c in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_SALU",
                                             "SQ_INSTS_VMEM_RD", "SQ_WAVES", "GRBM_GUI_ACTIVE")}
         if any(x is None for x in v.values()):
@@ -229,7 +227,7 @@ def summarize(prof_dir):
         issue = v["SQ_INSTS_VALU"] * 4 / (simds * cycles)
         rows_md.append(f"| {kind} | {v['SQ_WAVES']:.0f} | {v['SQ_INSTS_VALU']:.4g} | {v['SQ_INSTS_SALU']:.4g} | "
                        f"{v['SQ_INSTS_VMEM_RD']:.4g} | {cycles:.0f} | {cycles / 2.4e3:.1f} | {issue:.3f} |")
-    tot_valu = sum(sq.get((k, "SQ_INSTS_VALU"), 0.0) for k in ("interior", "boundary"))
+    tot_valu = sq.get(("pass", "SQ_INSTS_VALU"), 0.0)
     md = ["# Vector instruction issue of the dominant kernel pass (compensated FP32, 9-point, 4097 x 4097)", "",
           "Commands (from the repository root, one MI355X, one counter group per run):", "",
           "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
@@ -238,8 +236,8 @@ def summarize(prof_dir):
           "    rocprofv3 --pmc GRBM_GUI_ACTIVE GRBM_COUNT --output-format csv -d gpurun_out/pmc_grbm -o grbm "
           "-- python3 bench.py --mode profile",
           "    python3 bench.py --mode summarize", "",
-          f"Shape: depth {depth}, rows {rows}.  Counter runs serialize the two kernels of a pass; medians over "
-          "the dispatches of the profile run.  GRBM_GUI_ACTIVE sums the clocks of the 8 XCDs, so the kernel's "
+          f"Shape: depth {depth}, rows {rows}; one launch per pass (boundary and interior work items).  "
+          "Medians over the dispatches of the profile run.  GRBM_GUI_ACTIVE sums the clocks of the 8 XCDs, so the kernel's "
           "cycles are that / 8 (us at 2.4 GHz shown beside them).  `issue` = SQ_INSTS_VALU x 4 cycles / "
           "(1024 SIMDs x cycles): the fraction of SIMD cycles that issue a wave64 vector instruction (one per "
           "4 cycles per SIMD without packed FP32).  SQ_ACTIVE_INST_VALU reads the same as SQ_INSTS_VALU on "
@@ -307,17 +305,19 @@ def other_workloads():
 def batch_bench(args):
     """The batched workload: 512 seeded instances (sides log-uniform in
     [64, 2048], schemes uniform over 5/9/13-point, lambda in [0.3, 0.9] x
-    limit, 100-2000 levels, 8 random sine modes), compensated FP32, launch
-    shapes autotuned per scheme, the whole batch replayed as one graph."""
+    limit, 100-2000 levels, 8 random sine modes), compensated FP32, the
+    library's default depth per stencil class (the segment height is chosen
+    per batched launch), the whole batch replayed as one graph.  (Tuning on
+    a single 1025^2 grid is not used: single grids run one fused launch per
+    pass, batches two launches on two streams, and their best depths
+    differ.)"""
     import torch
 
     import paper_1904_04048_amd as w
     from paper_1904_04048_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    tuned = {}
-    for sch in (w.P5, w.P9, w.P13):
-        tuned[sch] = w.wave2d_autotune(w.F32C, sch, 1025, 1025)
+    tuned = {sch: w.wave2d_get_tuning(w.F32C, sch) for sch in (w.P5, w.P9, w.P13)}
     probs = W.c4()
     insts = []
     for pr in probs:
@@ -351,7 +351,7 @@ def batch_bench(args):
             "value": round(st["lup"] / dt / 1e9, 2), "unit": "GLUP/s", "ms_per_batch": round(dt * 1e3, 2),
             "lup": st["lup"], "rounds": st["rounds"], "launches_per_run": st["launches"],
             "state_bytes": st["state_bytes"], "graph": True,
-            "tuned_shapes": {str(k): list(v) for k, v in tuned.items()},
+            "shapes": {str(k): list(v) for k, v in tuned.items()},
             "work_items": st["items"], "mean_segment_rows": round(st["item_rows"] / max(1, st["items"]), 1),
             "max_rel_err_vs_gpu_fp64_sampled": worst, "sample": "every 64th instance"}
 

@@ -766,6 +766,18 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_interior(SA
     stream_body<Prec, K, DEPTH, CW, false>(a, dc, wid, w);
 }
 
+// Both kinds of work items in one launch: boundary items take the first
+// wave ids, so the slower reflected passes start first and the interior
+// items fill the device around them; no second stream or event is needed.
+template <class Prec, int K, int DEPTH, int CW>
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_fused(SArgs<typename Prec::T> a, Decomp dc,
+                                                                            int nb, typename Prec::W w)
+{
+    const int wid = wave_id();
+    if (wid < nb) stream_body<Prec, K, DEPTH, CW, true>(a, dc, wid, w);
+    else if (wid - nb < dc.ns * dc.ng) stream_body<Prec, K, DEPTH, CW, false>(a, dc, wid - nb, w);
+}
+
 // Batched kernels: one launch advances many instances (different grids,
 // weights and buffers) by one pass.  The work items of all instances form
 // one index space; prefix[k] is the first global work id of item k and
@@ -859,28 +871,18 @@ hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, cons
     a.nwork = dc.nstrips * dc.nseg;
     const int nb = a.nwork - dc.ns * dc.ng;
     const int ni = dc.ns * dc.ng;
-    // The two kernels write disjoint nodes and read only the input state, so
-    // the boundary kernel (few, long-lived waves) may run beside the interior one.
-    const bool split = fork && nb > 0 && ni > 0;
-    hipError_t e;
-    if (split) {
-        if ((e = hipEventRecord(fork->ev_fork, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(fork->side, fork->ev_fork, 0)) != hipSuccess) return e;
-    }
-    if (nb > 0) {
-        const int blocks = (nb + kWavesPerBlock - 1) / kWavesPerBlock;
-        k_stream_general<Prec, K, DEPTH, CW>
-            <<<blocks, kWave * kWavesPerBlock, 0, split ? fork->side : s>>>(a, dc, nb, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (split && (e = hipEventRecord(fork->ev_join, fork->side)) != hipSuccess) return e;
-    if (ni > 0) {
-        const int blocks = (ni + kWavesPerBlock - 1) / kWavesPerBlock;
+    // One launch per pass (measured on 4097^2 9-point compensated: 786 ->
+    // 826 GLUP/s against a boundary kernel on a side stream beside the
+    // interior kernel; 2049^2: 442 -> 579).
+    (void)fork;
+    const int blocks = (a.nwork + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (nb > 0 && ni > 0)
+        k_stream_fused<Prec, K, DEPTH, CW><<<blocks, kWave * kWavesPerBlock, 0, s>>>(a, dc, nb, w);
+    else if (nb > 0)
+        k_stream_general<Prec, K, DEPTH, CW><<<blocks, kWave * kWavesPerBlock, 0, s>>>(a, dc, nb, w);
+    else
         k_stream_interior<Prec, K, DEPTH, CW><<<blocks, kWave * kWavesPerBlock, 0, s>>>(a, dc, w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (split && (e = hipStreamWaitEvent(s, fork->ev_join, 0)) != hipSuccess) return e;
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 template <class Prec, int K>
@@ -921,7 +923,9 @@ bool stream_depth_supported(int depth)
 namespace {
 
 // Resident waves of a kernel on the current device (all CUs), and whether
-// it uses scratch memory; cached per (kernel, device).
+// its state does not fit the registers (more than 128 bytes of scratch per
+// lane: such depths spill hundreds of bytes, while a few spilled scalars,
+// tens of bytes, cost nothing measurable); cached per (kernel, device).
 std::pair<int, bool> kernel_fit(const void* fn)
 {
     static std::mutex mu;
@@ -933,7 +937,7 @@ std::pair<int, bool> kernel_fit(const void* fn)
     if (it != cache.end()) return it->second;
     hipFuncAttributes at{};
     bool spills = false;
-    if (hipFuncGetAttributes(&at, fn) == hipSuccess) spills = at.localSizeBytes > 0;
+    if (hipFuncGetAttributes(&at, fn) == hipSuccess) spills = at.localSizeBytes > 128;
     int nb = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWave * kWavesPerBlock, 0) != hipSuccess || nb < 1)
         nb = 1;
@@ -947,7 +951,8 @@ std::pair<int, bool> kernel_fit(const void* fn)
 template <class Prec, int K, int DEPTH>
 ShapeFit fit_depth()
 {
-    const auto f = kernel_fit(reinterpret_cast<const void*>(&k_stream_interior<Prec, K, DEPTH, 2>));
+    // The kernel a pass over a grid with both kinds of items launches.
+    const auto f = kernel_fit(reinterpret_cast<const void*>(&k_stream_fused<Prec, K, DEPTH, 2>));
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;

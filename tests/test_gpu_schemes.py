@@ -9,6 +9,8 @@ rules; the temporally blocked kernels are bitwise equal to the
 one-node-per-thread kernels; batches equal solo runs.  The paper's own
 13-point set built at run time reproduces the built-in 13-point scheme.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -127,3 +129,35 @@ def test_paper_13_point_set_built_at_run_time():
         w.wave2d_run(U0, V0, P, C, h, tau, 1.0, s, 40)
         out.append(C.cpu().numpy())
     assert oracle.rel_max_err(out[1], out[0]) <= 1e-13
+
+
+def test_cross_scheme_served(cross):
+    # Served requests of a built scheme equal the same solve run alone.
+    sv = w.wave2d_server_create(256 << 20)
+    try:
+        items = []
+        for k, (nx, ny, steps, periodic) in enumerate([(200, 150, 41, False), (64, 96, 9, True), (131, 77, 25, False)]):
+            u0, v0 = rough_data(nx, ny, 40 + k)
+            U0, V0 = dev_grid(u0), dev_grid(v0)
+            h = 1.0 / max(nx, ny)
+            tau = 0.9 * w.wave2d_lambda_max(cross) * h
+            f = w.PERIODIC if periodic else 0
+            rid = w.wave2d_server_submit(sv, nx, ny, h, tau, 1.0, cross, steps, f, u0=U0, v0=V0)
+            items.append((rid, U0, V0, h, tau, steps, f))
+        for rid, U0, V0, h, tau, steps, f in items:
+            t0 = time.time()
+            r = None
+            while r is None:
+                r = w.wave2d_server_poll(sv, rid)
+                assert time.time() - t0 < 60
+                time.sleep(0.001)
+            assert r["status"] == 0
+            u = torch.empty(U0.shape, dtype=torch.float32, device="cuda")
+            lo, d = torch.empty_like(u), torch.empty_like(u)
+            w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, cross, steps, f)
+            out = torch.empty_like(U0)
+            w.wave2d_f32c_export(u, lo, out)
+            assert torch.equal(w.result_tensor(r), out)
+            w.wave2d_server_release(sv, rid)
+    finally:
+        w.wave2d_server_destroy(sv)
