@@ -281,17 +281,17 @@ int fill_rows(int precision, int kind, int depth, int64_t nx, int64_t ny)
 // Shapes measured fastest on MI355X (256 CUs) for the grid sizes of the
 // standard workloads: sweeps of depth and of every segment height near the
 // best, repeated (the height of the last, partial segment of a column
-// makes neighbouring heights differ by up to 10%).  Used only on devices
-// with the same CU count.
+// makes neighbouring heights differ by up to 10%), step-loop rates with
+// one launch per pass.  Used only on devices with the same CU count.
 struct MeasuredShape {
     int precision, scheme;
     int64_t nx, ny;
     wave2d_tuning t;
 };
 const MeasuredShape kMeasured[] = {
-    {WAVE2D_F32C, WAVE2D_P9, 4097, 4097, {8, 40}},   // 855 GLUP/s
+    {WAVE2D_F32C, WAVE2D_P9, 4097, 4097, {8, 38}},   // 902 GLUP/s (40 rows: 891)
     {WAVE2D_F32C, WAVE2D_P9, 8193, 8193, {8, 68}},   // 1077
-    {WAVE2D_F32C, WAVE2D_P9, 2049, 2049, {6, 13}},   // 457
+    {WAVE2D_F32C, WAVE2D_P9, 2049, 2049, {6, 20}},   // 620 (13 rows: 605)
     {WAVE2D_F32C, WAVE2D_P5, 4097, 4097, {8, 40}},   // 890
     {WAVE2D_F32C, WAVE2D_P13, 4097, 4097, {6, 44}},  // 560
     {WAVE2D_F32C, WAVE2D_P13, 8193, 8193, {6, 112}}, // 778
