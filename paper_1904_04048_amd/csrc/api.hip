@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -345,8 +346,52 @@ void set_tuning_size_entry(int precision, int scheme, int64_t nx, int64_t ny, co
     g_tune_size[std::make_tuple(precision, scheme, nx, ny)] = t;
 }
 
+// Shapes kept across processes: with WAVE2D_TUNE_CACHE naming a file, each
+// line "precision scheme nx ny depth rows" is loaded before the first
+// lookup, and every autotuned shape is appended.  Lines that do not parse,
+// unknown or run-time-built schemes and unsupported shapes are skipped.
+std::once_flag g_cache_once;
+
+bool cacheable(int precision, int scheme, const wave2d_tuning& t)
+{
+    const bool paper = scheme == WAVE2D_P5 || scheme == WAVE2D_P9 || scheme == WAVE2D_P13 || scheme == WAVE2D_C9;
+    return (precision == WAVE2D_F64 || precision == WAVE2D_F32C) && paper && stream_depth_supported(t.depth) &&
+           t.rows >= 1;
+}
+
+void load_tune_cache()
+{
+    const char* path = std::getenv("WAVE2D_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        int prec, scheme, depth, rows;
+        long long nx, ny;
+        if (std::sscanf(line, "%d %d %lld %lld %d %d", &prec, &scheme, &nx, &ny, &depth, &rows) != 6) continue;
+        const wave2d_tuning t{depth, rows};
+        if (nx < 3 || ny < 3 || !cacheable(prec, scheme, t)) continue;
+        set_tuning_size_entry(prec, scheme, nx, ny, t);
+    }
+    std::fclose(f);
+}
+
+void save_tune_cache(int precision, int scheme, int64_t nx, int64_t ny, const wave2d_tuning& t)
+{
+    const char* path = std::getenv("WAVE2D_TUNE_CACHE");
+    if (!path || !*path || !cacheable(precision, scheme, t)) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %lld %lld %d %d\n", precision, scheme, (long long)nx, (long long)ny, t.depth, t.rows);
+    std::fclose(f);
+}
+
 wave2d_tuning tuning_for(int precision, int scheme, int64_t nx, int64_t ny)
 {
+    std::call_once(g_cache_once, load_tune_cache);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_size.find(std::make_tuple(precision, scheme, nx, ny));
     if (it != g_tune_size.end()) return it->second;

@@ -59,6 +59,7 @@ wave2d_tuning tuning_for(int precision, int scheme, int64_t nx, int64_t ny);
 bool stream_ok(const Grid& g, size_t elt);
 void set_tuning_entry(int precision, int scheme, const wave2d_tuning& t);
 void set_tuning_size_entry(int precision, int scheme, int64_t nx, int64_t ny, const wave2d_tuning& t);
+void save_tune_cache(int precision, int scheme, int64_t nx, int64_t ny, const wave2d_tuning& t);
 int get_device(int* dev);
 size_t align256(size_t v);
 int side_of(hipStream_t s, const Fork** out);

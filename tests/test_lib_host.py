@@ -149,3 +149,25 @@ def test_tuning_roundtrip(L):
     assert L.wave2d_set_tuning(1, 9, ctypes.byref(bad)) == -1
     bad = _lib.Tuning(2, 4)
     assert L.wave2d_set_tuning(1, 9, ctypes.byref(bad)) == -1
+
+
+def test_tune_cache_file_is_loaded(tmp_path):
+    # Shapes listed in WAVE2D_TUNE_CACHE become the per-size shapes of a new
+    # process; malformed lines, unknown schemes and unsupported depths are
+    # skipped.  (Run in a child process: the file is read once per process.)
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("1 9 777 555 6 24\n"
+                     "garbage line\n"
+                     "1 13 300 200 5 16\n"      # depth 5 is not supported
+                     "0 1009 300 200 4 16\n"    # not a paper scheme
+                     "0 13 300 200 4 16\n")
+    code = ("import paper_1904_04048_amd as w\n"
+            "print(w.wave2d_get_tuning(w.F32C, 9, 777, 555), w.wave2d_get_tuning(w.F64, 13, 300, 200),"
+            " w.wave2d_get_tuning(w.F32C, 13, 300, 200)[0] != 5)\n")
+    env = dict(os.environ, WAVE2D_TUNE_CACHE=str(cache))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "(6, 24) (4, 16) True", out.stdout
