@@ -171,3 +171,19 @@ def test_tune_cache_file_is_loaded(tmp_path):
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "(6, 24) (4, 16) True", out.stdout
+
+
+def test_default_depth_rule():
+    # Without a measured shape for the size, the default depth follows the
+    # scheme and precision; the double-precision 13-point kernel goes deeper
+    # from 2^23 nodes up.
+    import paper_1904_04048_amd as w
+    assert w.wave2d_get_tuning(w.F64, w.P13, 2049, 2049)[0] == 4
+    assert w.wave2d_get_tuning(w.F64, w.P13, 4096, 2048)[0] == 6
+    assert w.wave2d_get_tuning(w.F64, w.P13, 4095, 2048)[0] == 4
+    assert w.wave2d_get_tuning(w.F64, w.P9, 2049, 2049)[0] == 8
+    assert w.wave2d_get_tuning(w.F32C, w.P13, 2049, 2049)[0] == 6
+    assert w.wave2d_get_tuning(w.F32C, w.P5, 1000, 3000)[0] == 8
+    for p in (w.F64, w.F32C):
+        for s in (w.P5, w.P9, w.P13):
+            assert w.wave2d_get_tuning(p, s, 3000, 3001)[1] >= 8
