@@ -5,8 +5,10 @@
   closed-form discrete solution for sine-series data (oracle.modes), which
   holds at any size and is pinned to the full-grid oracle on small grids.
 * 13-point Gaussian, 3000 levels: the 1025^2 copy against the full-grid
-  oracle (FP64 and compensated FP32); the 8193^2 run compensated FP32
-  against GPU FP64 (no closed form exists for this data).
+  oracle (FP64 and compensated FP32); the 8193^2 run: FP64 against the
+  scheme's conserved energy (tests/test_oracle_energy.py), its value at the
+  first levels taken from the oracle, and compensated FP32 against GPU FP64
+  (no closed form exists for this data).
 """
 import math
 
@@ -18,6 +20,7 @@ import oracle
 import paper_1904_04048_amd as w
 from oracle import modes
 from paper_1904_04048_amd import workloads as W
+from tests.test_oracle_energy import energy
 
 pytestmark = pytest.mark.gpu
 
@@ -72,14 +75,22 @@ def test_thirteen_point_1025_copy_against_oracle():
     assert oracle.rel_max_err(_f32c(p, U0, V0).cpu().numpy(), rc) <= 1e-5
 
 
-def test_thirteen_point_8193_f32c_against_gpu_fp64():
+def test_thirteen_point_8193_energy_and_f32c():
     p = W.c3()
     u0, v0 = p.data()
     U0, V0 = torch.from_numpy(u0).cuda(), torch.from_numpy(v0).cuda()
-    del u0, v0
-    _, C = _f64(p, U0, V0)
+    P, C = _f64(p, U0, V0)
     out = _f32c(p, U0, V0)
     nr = w.wave2d_norms(out, C)
     assert nr[0] / nr[1] <= 1e-5
-    # FP64 energy-type sanity: the pulse neither vanished nor blew up
+    # the pulse neither vanished nor blew up
     assert 1e-3 < nr[1] < 10.0
+    del out
+    # The discrete energy after 3000 levels equals its value at levels 1-2,
+    # which the oracle computes from the initial data.
+    um, u = oracle.run(u0, v0, p.h, p.tau, p.c, p.scheme, 2)
+    del u0, v0
+    e0 = energy(um, u, p.h, p.tau, p.c, p.scheme)
+    del um, u
+    eN = energy(P.cpu().numpy(), C.cpu().numpy(), p.h, p.tau, p.c, p.scheme)
+    assert abs(eN - e0) <= 1e-10 * e0, (eN, e0)
