@@ -537,7 +537,7 @@ def main():
     kernel_glups = p.interior * depth / t_launch / 1e9
     traffic = traffic_record(kernel_cfg)
     # The pass is bound by vector instruction issue (SQ counters: the SIMDs
-    # issue VALU work on 80% of the kernel's cycles), not by HBM: it advances
+    # issue VALU work on 77% of the kernel's cycles), not by HBM: it advances
     # `depth` levels per read of the state.
     lup_launch = p.interior * depth
     achieved_tflops = FLOPS_PER_LUP_F32C_9PT * lup_launch / t_launch / 1e12

@@ -272,35 +272,54 @@ int fill_rows(int precision, int kind, int depth, int64_t nx, int64_t ny)
     const ShapeFit f = stream_shape_fit(precision, kind, depth);
     if (f.slots < 1 || f.strip_cols < 1) return 32;
     const int64_t nstrips = (nx + f.strip_cols - 1) / f.strip_cols;
-    const double target = (f.simd_waves >= 3) ? 1.5 : 2.0;
-    const int64_t segs = std::max<int64_t>(1, (int64_t)(target * f.slots) / nstrips);
-    const int64_t r = (ny + segs - 1) / segs;
     const int64_t lo = std::max(8, 2 * f.halo_rows);
-    return (int)std::min<int64_t>(64, std::max<int64_t>(lo, r));
+    if (f.simd_waves >= 3) {
+        const int64_t segs = std::max<int64_t>(1, (int64_t)(1.5 * f.slots) / nstrips);
+        const int64_t r = (ny + segs - 1) / segs;
+        return (int)std::min<int64_t>(64, std::max<int64_t>(lo, r));
+    }
+    // Two waves per SIMD: the longest segments whose work items fill a
+    // whole number of rounds of the resident waves (a launch takes
+    // ceil(items / slots) item times, and longer segments recompute fewer
+    // warm-up rows).  Measured on 4097^2: one round (75 rows) beats two
+    // (38) by 3-7% for the compensated 5- and 9-point kernels and the
+    // double-precision 9-point one (its 5-point kernel prefers two rounds),
+    // and for the 13-point kernels 81 rows (one round) beats 44 (1.8
+    // rounds) by 4-11%.  Very tall segments lose again: on 6001^2 the
+    // compensated 9-point kernel ran 4% slower at 163 rows (one round) than
+    // at 82 (two), hence the cap.
+    constexpr int64_t kMaxRows = 128;
+    for (int64_t k = 1; k <= 64; ++k) {
+        const int64_t segs = k * f.slots / nstrips;
+        if (segs < 1) continue;
+        const int64_t r = (ny + segs - 1) / segs;
+        if (r <= kMaxRows) return (int)std::max(lo, r);
+    }
+    return (int)std::max<int64_t>(lo, 64);
 }
 
 // Shapes measured fastest on MI355X (256 CUs) for the grid sizes of the
 // standard workloads: sweeps of depth and of every segment height near the
 // best, repeated (the height of the last, partial segment of a column
-// makes neighbouring heights differ by up to 10%), step-loop rates with
-// one launch per pass.  Used only on devices with the same CU count.
+// makes neighbouring heights differ by up to 10%), per-pass rates of
+// back-to-back passes (one launch each) after an untimed warm-up.  Used only on devices with the same CU count.
 struct MeasuredShape {
     int precision, scheme;
     int64_t nx, ny;
     wave2d_tuning t;
 };
 const MeasuredShape kMeasured[] = {
-    {WAVE2D_F32C, WAVE2D_P9, 4097, 4097, {8, 38}},   // 902 GLUP/s (40 rows: 891)
-    {WAVE2D_F32C, WAVE2D_P9, 8193, 8193, {8, 68}},   // 1077
-    {WAVE2D_F32C, WAVE2D_P9, 2049, 2049, {6, 20}},   // 620 (13 rows: 605)
-    {WAVE2D_F32C, WAVE2D_P5, 4097, 4097, {8, 40}},   // 890
-    {WAVE2D_F32C, WAVE2D_P13, 4097, 4097, {6, 44}},  // 560
-    {WAVE2D_F32C, WAVE2D_P13, 8193, 8193, {6, 112}}, // 778
-    {WAVE2D_F64, WAVE2D_P9, 4097, 4097, {8, 40}},    // 821
-    {WAVE2D_F64, WAVE2D_P5, 4097, 4097, {8, 40}},    // 864
-    {WAVE2D_F64, WAVE2D_P13, 4097, 4097, {6, 56}},   // 504 (depth 4: 452)
-    {WAVE2D_F64, WAVE2D_P13, 8193, 8193, {6, 128}},  // 579 (depth 4: 480)
-    {WAVE2D_F64, WAVE2D_P13, 2049, 2049, {4, 24}},   // 297 (depth 6: 276)
+    {WAVE2D_F32C, WAVE2D_P9, 4097, 4097, {8, 75}},    // 938 GLUP/s per pass (38 rows: 906)
+    {WAVE2D_F32C, WAVE2D_P9, 8193, 8193, {8, 100}},   // 1121 (68 rows: 1070)
+    {WAVE2D_F32C, WAVE2D_P9, 2049, 2049, {6, 19}},    // 654 (20 rows: 625)
+    {WAVE2D_F32C, WAVE2D_P5, 4097, 4097, {8, 75}},    // 975 (40 rows: 911)
+    {WAVE2D_F32C, WAVE2D_P13, 4097, 4097, {6, 81}},   // 612 (44 rows: 551)
+    {WAVE2D_F32C, WAVE2D_P13, 8193, 8193, {6, 161}},  // 796 (112 rows: 771)
+    {WAVE2D_F64, WAVE2D_P9, 4097, 4097, {8, 75}},     // 890 (40 rows: 848)
+    {WAVE2D_F64, WAVE2D_P5, 4097, 4097, {8, 38}},     // 966 (75 rows: 918)
+    {WAVE2D_F64, WAVE2D_P13, 4097, 4097, {6, 81}},    // 548 (56 rows: 528)
+    {WAVE2D_F64, WAVE2D_P13, 8193, 8193, {6, 161}},   // 696 (128 rows: 662)
+    {WAVE2D_F64, WAVE2D_P13, 2049, 2049, {4, 20}},    // 337 (24 rows: 303)
 };
 
 int device_cus()
