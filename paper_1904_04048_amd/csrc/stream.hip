@@ -1006,7 +1006,7 @@ int batch_rows(int rows_min, const std::vector<BatchInst>& insts, int slots_i)
 {
     constexpr int HP = halo_cols<R, DEPTH>();
     constexpr int SW = kWave * 2 - 2 * HP;
-    static const int cand[] = {12, 16, 24, 32, 48, 64, 80, 96, 128};
+    static const int cand[] = {12, 16, 24, 32, 48, 64, 80, 96, 128, 160, 192};
     const double slots = slots_i;
     auto cost = [&](int r) {
         double items = 0;
