@@ -317,6 +317,8 @@ const MeasuredShape kMeasured[] = {
     {WAVE2D_F32C, WAVE2D_P13, 8193, 8193, {6, 161}},  // 796 (112 rows: 771)
     {WAVE2D_F64, WAVE2D_P9, 4097, 4097, {8, 75}},     // 890 (40 rows: 848)
     {WAVE2D_F64, WAVE2D_P5, 4097, 4097, {8, 38}},     // 966 (75 rows: 918)
+    {WAVE2D_F64, WAVE2D_P9, 8193, 8193, {8, 149}},    // 1028 (100 rows: 1005)
+    {WAVE2D_F64, WAVE2D_P5, 8193, 8193, {8, 149}},    // 1056 (100 rows: 1044)
     {WAVE2D_F64, WAVE2D_P13, 4097, 4097, {6, 81}},    // 548 (56 rows: 528)
     {WAVE2D_F64, WAVE2D_P13, 8193, 8193, {6, 161}},   // 696 (128 rows: 662)
     {WAVE2D_F64, WAVE2D_P13, 2049, 2049, {4, 20}},    // 337 (24 rows: 303)
