@@ -99,12 +99,12 @@ def test_run_f32c_matches_oracle(scheme, shape, steps):
     assert padding_intact(u) and padding_intact(lo) and padding_intact(d) and padding_intact(out)
 
 
-DEPTHS = [1, 2, 3, 4, 6]
+DEPTHS = [1, 2, 3, 4, 6, 8]
 
 
 @pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
 @pytest.mark.parametrize("depth", DEPTHS)
-@pytest.mark.parametrize("rows", [8, 13, 64])
+@pytest.mark.parametrize("rows", [8, 13, 64, 161])
 def test_stream_fp64_bitwise_equals_simple(scheme, depth, rows):
     ny, nx = 157, 263
     u0, v0 = rough_data(nx, ny, 4)
@@ -124,7 +124,7 @@ def test_stream_fp64_bitwise_equals_simple(scheme, depth, rows):
 
 @pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
 @pytest.mark.parametrize("depth", DEPTHS)
-@pytest.mark.parametrize("rows", [8, 13, 64])
+@pytest.mark.parametrize("rows", [8, 13, 64, 161])
 def test_stream_f32c_bitwise_equals_simple(scheme, depth, rows):
     ny, nx = 157, 263
     (u0, v0), _ = smooth_data(nx, ny, 5)

@@ -79,7 +79,7 @@ def test_periodic_fp64_and_f32c_match_oracle(scheme, shape):
 
 
 @pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
-@pytest.mark.parametrize("depth", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 6, 8])
 def test_periodic_stream_equals_simple(scheme, depth):
     for (nx, ny) in [(260, 131), (128, 9), (6, 40), (64, 64)]:
         u0, v0 = rough_data(nx, ny, nx + ny)

@@ -69,7 +69,7 @@ def test_cross_scheme_matches_oracle(cross, shape, periodic, conv):
     assert oracle.rel_max_err(out.cpu().numpy(), rc) <= 1e-5
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 6, 8])
 def test_cross_scheme_stream_equals_simple(cross, depth):
     for (nx, ny) in [(260, 131), (131, 70), (64, 64)]:
         u0, v0 = rough_data(nx, ny, nx + 3 * ny)
