@@ -94,3 +94,18 @@ def test_thirteen_point_8193_energy_and_f32c():
     del um, u
     eN = energy(P.cpu().numpy(), C.cpu().numpy(), p.h, p.tau, p.c, p.scheme)
     assert abs(eN - e0) <= 1e-10 * e0, (eN, e0)
+
+
+def test_profiles_match_the_benchmark_shape():
+    # The committed counter summary keys its HBM traffic by the kernel
+    # sources and the launch shape; on a 256-CU device the benchmark's
+    # default shape must be the one it was taken with, or the benchmark
+    # reports no traffic.
+    import bench
+    if torch.cuda.get_device_properties(0).multi_processor_count != 256:
+        pytest.skip("the measured shapes apply to 256-CU devices")
+    p = W.c2()
+    depth, rows = w.wave2d_get_tuning(w.F32C, p.scheme, p.nx, p.ny)
+    cfg = {"kernel": bench.KERNEL_NAME, "depth": depth, "rows": rows, "grid": [p.nx, p.ny],
+           "source": bench.kernel_source_hash()}
+    assert bench.traffic_record(cfg) is not None, cfg
