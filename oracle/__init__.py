@@ -204,7 +204,17 @@ def norms(a, b):
 
 
 def rel_max_err(a, b) -> float:
-    """max|a-b| / max|b| (the tolerance measure used for GPU parity)."""
+    """max|a-b| / max|b| (the tolerance measure used for GPU parity).
+
+    Raises ValueError when either array holds a NaN or an infinity: a result
+    that was never written (the GPU tests pre-fill outputs with NaN) or that
+    blew up must fail a parity check, never pass it."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    for name, x in (("result", a), ("reference", b)):
+        if not np.isfinite(x).all():
+            bad = int(x.size - np.count_nonzero(np.isfinite(x)))
+            raise ValueError(f"{name} holds {bad} non-finite value(s) of {x.size}")
     n = norms(a, b)
     return float(n[0] / n[1]) if n[1] > 0 else float(n[0])
 
