@@ -16,16 +16,17 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5, P9, P13, PERIODIC,
-                   BatchStats, Instance, Request, Result, ServerStats, Tuning, Wave2dError)
+from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, BATCH_ROUNDS, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5,
+                   P9, P13, PERIODIC, BatchStats, Instance, Request, Result, ServerStats, Tuning, Wave2dError)
 
 __all__ = [
     "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE", "PERIODIC",
     "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_work_bytes", "wave2d_first_step",
-    "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_export",
+    "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step",
+    "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
-    "wave2d_release", "wave2d_autotune", "wave2d_batch_create", "wave2d_batch_run", "wave2d_batch_stats_get",
-    "wave2d_batch_destroy", "BATCH_GRAPH", "wave2d_sine_series", "wave2d_server_create", "wave2d_server_submit",
+    "wave2d_release", "wave2d_autotune", "wave2d_batch_create", "wave2d_batch_run", "wave2d_batch_stats_get", "wave2d_batch_autotune",
+    "wave2d_batch_destroy", "BATCH_GRAPH", "BATCH_ROUNDS", "wave2d_sine_series", "wave2d_server_create", "wave2d_server_submit",
     "wave2d_server_poll", "wave2d_server_release", "wave2d_server_stats_get", "wave2d_server_destroy",
 ]
 
@@ -219,6 +220,15 @@ def wave2d_batch_stats_get(batch):
     st = BatchStats()
     _lib.check(_lib.load().wave2d_batch_stats_get(batch, ctypes.byref(st)))
     return {k: getattr(st, k) for k, _ in BatchStats._fields_}
+
+
+def wave2d_batch_autotune(batch):
+    """Time the batch with each candidate segment cap; keep and return the fastest."""
+    import torch
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    cap = ctypes.c_int32(0)
+    _lib.check(_lib.load().wave2d_batch_autotune(batch, s, ctypes.byref(cap)))
+    return cap.value
 
 
 def wave2d_batch_destroy(batch):

@@ -24,6 +24,7 @@ SZ = ctypes.c_size_t
 
 
 BATCH_GRAPH = 0x10000
+BATCH_ROUNDS = 0x20000
 
 
 class Tuning(ctypes.Structure):
@@ -41,7 +42,9 @@ class Instance(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("instances", ctypes.c_int64), ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("lup", ctypes.c_int64), ("state_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64),
-                ("items", ctypes.c_int64), ("item_rows", ctypes.c_int64)]
+                ("items", ctypes.c_int64), ("item_rows", ctypes.c_int64), ("persistent_items", ctypes.c_int64),
+                ("stalled_waits", ctypes.c_int64), ("persistent_lup", ctypes.c_int64),
+                ("persistent_bytes", ctypes.c_int64), ("last_persistent_ms", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -85,6 +88,7 @@ _SIGS = {
     "wave2d_batch_create": (I, [P, I64, U32, P]),
     "wave2d_batch_run": (I, [P, P]),
     "wave2d_batch_stats_get": (I, [P, P]),
+    "wave2d_batch_autotune": (I, [P, P, P]),
     "wave2d_batch_destroy": (I, [P]),
     "wave2d_sine_series": (I, [I64, I64, I64, ctypes.c_int32, P, P, P, P]),
     "wave2d_server_create": (I, [SZ, U32, P]),

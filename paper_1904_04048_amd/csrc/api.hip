@@ -213,7 +213,9 @@ StepW32 step_w32(const Params& p)
     w.w11 = (float)(2.0 * p.wa[1]);
     w.w20 = (float)(2.0 * p.wa[2]);
     w.wc = -4.0f * (w.w10 + w.w11 + w.w20);
-    w.wx = (float)(2.0 * p.wa[0] + 4.0 * p.wa[1] + 8.0 * p.wa[2]);
+    const double wx = 2.0 * p.wa[0] + 4.0 * p.wa[1] + 8.0 * p.wa[2];
+    w.wx = (float)wx;
+    w.wxl = (float)(wx - (double)w.wx);
     return w;
 }
 
@@ -571,12 +573,7 @@ int run_steps_f64(const Params& p, uint32_t flags, int64_t steps, double* up, do
         // In place: level k+1 overwrites level k-1, then the roles swap.
         double* a = up;
         double* b = uc;
-        const Fork* fk = nullptr;
-        if (!simple) {
-            int r = side_of(s, &fk);
-            if (r) return r;
-        }
-        const StreamShape sh{1, tn.rows, fk};
+        const StreamShape sh{1, tn.rows};
         for (int64_t k = 0; k < steps; ++k) {
             if (simple) W2D_HIP(simple_step_f64(g, p.kind, w, a, b, a, s));
             else W2D_HIP(stream_step_f64(g, p.kind, w, sh, a, b, a, nullptr, s));
@@ -591,13 +588,11 @@ int run_steps_f64(const Params& p, uint32_t flags, int64_t steps, double* up, do
     const size_t stride = align256((size_t)g.ld * g.ny * sizeof(double));
     double* wp = (double*)base;
     double* wc = (double*)(base + stride);
-    const Fork* fk;
-    if ((r = side_of(s, &fk))) return r;
     bool needs_copy;
     const std::vector<int> passes = plan_passes(steps, tn.depth, &needs_copy);
     double *ip = up, *ic = uc, *op = wp, *oc = wc;
     for (int d : passes) {
-        const StreamShape sh{d, tn.rows, fk};
+        const StreamShape sh{d, tn.rows};
         W2D_HIP(stream_step_f64(g, p.kind, w, sh, ip, ic, op, oc, s));
         std::swap(ip, op);
         std::swap(ic, oc);
@@ -621,8 +616,6 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
     float* wl = (float*)(base + stride);
     float* wd = (float*)(base + 2 * stride);
     const bool simple = (flags & WAVE2D_KERNEL_SIMPLE) || !stream_ok(g, sizeof(float));
-    const Fork* fk = nullptr;
-    if (!simple && (r = side_of(s, &fk))) return r;
     const wave2d_tuning tn = tuning_for(WAVE2D_F32C, p.scheme, g.nx, g.ny);
     bool needs_copy = false;
     std::vector<int> passes;
@@ -631,7 +624,7 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
     float *iu = u, *il = lo, *id = d, *ou = wu, *ol = wl, *od = wd;
     for (int dd : passes) {
         if (simple) W2D_HIP(simple_step_f32c(g, p.kind, w, iu, il, id, ou, ol, od, s));
-        else W2D_HIP(stream_step_f32c(g, p.kind, w, StreamShape{dd, tn.rows, fk}, iu, il, id, ou, ol, od, s));
+        else W2D_HIP(stream_step_f32c(g, p.kind, w, StreamShape{dd, tn.rows}, iu, il, id, ou, ol, od, s));
         std::swap(iu, ou);
         std::swap(il, ol);
         std::swap(id, od);

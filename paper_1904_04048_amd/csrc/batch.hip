@@ -1,19 +1,25 @@
 // Batches of compensated-FP32 solves and the launch-shape autotuner.
 //
-// A batch is planned once: instances are grouped by stencil class and tuned
-// launch shape, and the run is cut into rounds.  In every round each
-// unfinished instance advances by one pass of up to its class's depth; all
-// instances of a class that take the same depth share one launch of the
-// batched streaming kernels (their work items form one index space, so
-// small and large grids load-balance inside the launch).  Boundary-strip
-// items run on a side stream beside the interior items.  The tables of
-// every launch are built on the host and uploaded once; with
-// WAVE2D_BATCH_GRAPH the whole sequence is captured into one hipGraph.
+// A batch is planned once.  Every instance's levels after the first step
+// are split into passes of its stencil class's depth plus a remainder; the
+// remainder passes run first, in rounds of batched launches (all instances
+// of a class taking the same depth share one launch whose work items form
+// one index space), and all full-depth passes of all instances then run in
+// ONE persistent launch: instances are pinned to the device's XCCs (L2
+// domains) by a greedy balance of their work, each XCC works through its own
+// queue of (instance, pass) tasks in pass-major order, and a wave waits only
+// for the previous pass of its own instance (see k_stream_persist).  First
+// steps, and the copies that leave each final state in the caller's
+// arrays, are one launch each.  Tables are built on the host and uploaded
+// once; with WAVE2D_BATCH_GRAPH the whole sequence is captured into one
+// hipGraph.  WAVE2D_BATCH_ROUNDS runs every pass in rounds instead (the
+// same passes, bit for bit).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -45,6 +51,18 @@ struct InstRec {
     bool ends_in_b;
 };
 
+// A wait of the persistent kernels gives up after this long (100 MHz
+// real-time clock ticks: 2 s; a healthy wait lasts at most a few item times,
+// about a millisecond); a wait that gives up is counted, its item is
+// skipped and every later wait of the launch gives up at once, so a launch
+// always ends.  WAVE2D_BATCH_WAIT_MS overrides it (tests of that path).
+constexpr long long kWaitTicks = 200000000LL;
+constexpr int kClasses = 3;  // stencil classes KIND5, KIND9, KIND13: one persistent launch each
+
+// Tallest segment of a persistent work item (taller grids are cut into
+// equal segments of at most this many rows).
+constexpr int kPersistRowsCap = 160;
+
 }  // namespace
 
 struct wave2d_batch {
@@ -61,6 +79,26 @@ struct wave2d_batch {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     hipStream_t capture = nullptr;  // private stream the graph is captured on
+    // One-launch parts of a run (offsets into `tables`).
+    size_t first_recs = 0, first_prefix = 0;
+    int first_count = 0, first_blocks = 0;
+    size_t copy_recs = 0, copy_prefix = 0;
+    int copy_count = 0, copy_blocks = 0;
+    bool persist = false;
+    // Per stencil class: whether it has persistent work, its queue offsets
+    // and item counts, and its counter block (n_ctr ints each).
+    size_t p_insts = 0, p_tasks = 0, p_qoff[kClasses] = {}, p_qn[kClasses] = {}, p_ctr[kClasses] = {};
+    bool p_has[kClasses] = {};
+    int n_ctr = 0;
+    long long wait_ticks = kWaitTicks;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the persistent launch
+    bool ran = false;
+    // Persistent plan inputs: full passes and the parity of the first one
+    // per instance, and the tallest segment of a work item.
+    std::vector<int64_t> full;
+    std::vector<int> par0;
+    int rows_cap = kPersistRowsCap;
+    int64_t p_item_rows = 0;
 };
 
 namespace {
@@ -73,15 +111,154 @@ int largest_supported(int d)
     return 1;
 }
 
-int enqueue(wave2d_batch* b, hipStream_t s)
+// Whether the workgroups of a launch land on exactly the kPersistQueues
+// XCCs 0..kPersistQueues-1 (one probe per device): the persistent kernel
+// keys its queues on them.
+bool xcc_layout_ok(int dev)
 {
-    // First steps (fused with the state split), one launch per instance.
-    for (const InstRec& r : b->inst)
-        W2D_HIP(simple_first_step_f32c(r.p.g, r.p.kind, r.fw, r.in.u0, r.in.v0, r.in.u, r.in.lo, r.in.d, s));
+    static std::mutex mu;
+    static std::map<int, bool> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    bool ok = false;
+    const int n = 64 * kPersistQueues;
+    int* d = nullptr;
+    if (hipMalloc(&d, n * sizeof(int)) == hipSuccess) {
+        std::vector<int> h(n, -1);
+        if (xcc_probe(d, n, nullptr) == hipSuccess &&
+            hipMemcpy(h.data(), d, n * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
+            std::vector<int> cnt(kPersistQueues, 0);
+            ok = true;
+            for (int v : h) {
+                if (v < 0 || v >= kPersistQueues) ok = false;
+                else ++cnt[v];
+            }
+            for (int c : cnt) ok = ok && c > 0;
+        }
+        (void)hipFree(d);
+    }
+    (void)hipGetLastError();
+    cache[dev] = ok;
+    return ok;
+}
+
+// Segment height of an instance's persistent items: the whole grid up to
+// `cap` rows, else the grid cut into equal segments of at most `cap` rows.
+int persist_rows(int ny, int cap)
+{
+    if (ny <= cap) return ny;
+    const int nseg = (ny + cap - 1) / cap;
+    return (ny + nseg - 1) / nseg;
+}
+
+// Tables of the persistent launch for segments of at most `cap` rows:
+// instance records, tasks in per-queue pass-major order, queue offsets and
+// item counts (the layout does not depend on `cap`, only the contents).
+struct PersistPlan {
+    std::vector<unsigned char> recs;
+    std::vector<PersistTask> tasks;     // all classes, class by class
+    std::vector<int> qoff[kClasses];    // per class: task index ranges of the queues (absolute)
+    std::vector<int> qn[kClasses];      // per class: items per queue
+    int64_t items = 0, item_rows = 0;
+};
+
+// The invariants the persistent kernel relies on: per class and queue, the
+// tasks [qoff[q], qoff[q+1]) cover items 0 .. qn[q]-1 in order (each task's
+// first item is the previous task's end), every task's instance belongs to
+// the class, and its wait count is a whole number of that instance's passes.
+int check_plan(const wave2d_batch* b, const PersistPlan& pl, const std::vector<int>& items)
+{
+    for (int c = 0; c < kClasses; ++c)
+        for (int q = 0; q < kPersistQueues; ++q) {
+            int64_t next = 0;
+            for (int t = pl.qoff[c][q]; t < pl.qoff[c][q + 1]; ++t) {
+                const PersistTask& k = pl.tasks[(size_t)t];
+                if (k.inst < 0 || (size_t)k.inst >= b->inst.size() || b->inst[(size_t)k.inst].p.kind != c ||
+                    k.first != next || items[(size_t)k.inst] < 1 || k.need % items[(size_t)k.inst] != 0)
+                    return fail(WAVE2D_EDEVICE, "persistent plan inconsistent at class %d queue %d task %d", c, q, t);
+                next += items[(size_t)k.inst];
+            }
+            if (next != pl.qn[c][q]) return fail(WAVE2D_EDEVICE, "persistent plan: queue %d item count", q);
+        }
+    return WAVE2D_OK;
+}
+
+int plan_persist(const wave2d_batch* b, int cap, PersistPlan* pl)
+{
+    const size_t ni = b->inst.size();
+    const size_t isz = persist_inst_size();
+    pl->recs.assign(ni * isz, 0);
+    pl->tasks.clear();
+    pl->items = pl->item_rows = 0;
+    std::vector<int> items(ni, 0);
+    std::vector<double> cost(ni, 0.0);
+    for (size_t i = 0; i < ni; ++i) {
+        const InstRec& rc = b->inst[i];
+        float* s0[3] = {rc.in.u, rc.in.lo, rc.in.d};
+        float* s1[3] = {rc.bu, rc.bl, rc.bd};
+        int nb = 0, rows_used = 0;
+        const int D = persist_depth(rc.p.kind);
+        const int R = rc.p.kind == KIND13 ? 2 : 1;
+        items[i] = persist_inst(rc.p.g, rc.p.kind, step_w32(rc.p), persist_rows(rc.p.g.ny, cap), s0, s1,
+                                pl->recs.data() + i * isz, &nb, &rows_used);
+        // Work model: an item streams rows + R (D - 1) + 2R + 1 rows of D
+        // levels, each about 2R + 1 times the 5-point work.
+        cost[i] = (double)b->full[i] * items[i] * (rows_used + R * (D - 1) + 2 * R + 1) * D * (2 * R + 1);
+        pl->items += b->full[i] * items[i];
+        pl->item_rows += b->full[i] * items[i] * (int64_t)rows_used;
+    }
+    // Per class, pin instances to queues: largest work first onto the
+    // least-loaded queue; then each queue's tasks in pass-major order.
+    std::vector<size_t> order(ni);
+    for (size_t i = 0; i < ni; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    for (int c = 0; c < kClasses; ++c) {
+        std::vector<double> load(kPersistQueues, 0.0);
+        std::vector<std::vector<size_t>> members(kPersistQueues);
+        for (size_t i : order) {
+            if (b->full[i] == 0 || b->inst[i].p.kind != c) continue;
+            const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[q] += cost[i];
+            members[q].push_back(i);
+        }
+        pl->qoff[c].assign(kPersistQueues + 1, 0);
+        pl->qn[c].assign(kPersistQueues, 0);
+        for (int q = 0; q < kPersistQueues; ++q) {
+            pl->qoff[c][q] = (int)pl->tasks.size();
+            int64_t maxp = 0;
+            for (size_t i : members[q]) maxp = std::max(maxp, b->full[i]);
+            int64_t first = 0;
+            for (int64_t p = 0; p < maxp; ++p)
+                for (size_t i : members[q]) {
+                    if (p >= b->full[i]) continue;
+                    pl->tasks.push_back(
+                        PersistTask{(int)i, (int)((b->par0[i] + p) & 1), (int)(p * items[i]), (int)first});
+                    first += items[i];
+                }
+            if (first >= (int64_t(1) << 31))
+                return fail(WAVE2D_EINVAL, "batch too large for one persistent launch (%lld items on one XCC)",
+                            (long long)first);
+            pl->qn[c][q] = (int)first;
+        }
+        pl->qoff[c][kPersistQueues] = (int)pl->tasks.size();
+    }
+    return check_plan(b, *pl, items);
+}
+
+// timing: record the batch's events around the persistent launches (not
+// inside a graph capture: events recorded by graph nodes cannot be timed).
+int enqueue(wave2d_batch* b, hipStream_t s, bool timing)
+{
+    char* base = (char*)b->tables;
+    for (int c = 0; c < kClasses; ++c)
+        if (b->p_has[c]) W2D_HIP(fill_i32((int*)(base + b->p_ctr[c]), b->n_ctr, 0, s));
+    // First steps (fused with the state split) of every instance: one launch.
+    W2D_HIP(first_step_f32c_batch((const FirstRecF32C*)(base + b->first_recs), (const int*)(base + b->first_prefix),
+                                  b->first_count, b->first_blocks, s));
     const Fork* fk = nullptr;
     int rc;
-    if ((rc = side_of(s, &fk))) return rc;
-    const char* base = (const char*)b->tables;
+    if (!b->rounds.empty() && (rc = side_of(s, &fk))) return rc;
     for (const Round& rd : b->rounds) {
         bool any_gen = false;
         for (size_t k = rd.first; k < rd.last; ++k) any_gen |= !b->launches[k].interior;
@@ -99,8 +276,17 @@ int enqueue(wave2d_batch* b, hipStream_t s)
             W2D_HIP(hipStreamWaitEvent(s, fk->ev_join, 0));
         }
     }
-    for (const InstRec& r : b->inst)
-        if (r.ends_in_b) W2D_HIP(copy_f32x3(r.p.g, r.bu, r.bl, r.bd, r.in.u, r.in.lo, r.in.d, s));
+    if (b->persist) {
+        if (timing) W2D_HIP(hipEventRecord(b->ev0, s));
+        for (int c = kClasses - 1; c >= 0; --c)
+            if (b->p_has[c])
+                W2D_HIP(persist_launch(c, base + b->p_insts, (const PersistTask*)(base + b->p_tasks),
+                                       (const int*)(base + b->p_qoff[c]), (const int*)(base + b->p_qn[c]),
+                                       (int*)(base + b->p_ctr[c]), b->wait_ticks, s));
+        if (timing) W2D_HIP(hipEventRecord(b->ev1, s));
+    }
+    W2D_HIP(copy_f32x3_batch((const CopyRec3*)(base + b->copy_recs), (const int*)(base + b->copy_prefix),
+                             b->copy_count, b->copy_blocks, s));
     return WAVE2D_OK;
 }
 
@@ -113,7 +299,8 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
     if (!out) return fail(WAVE2D_EINVAL, "out is NULL");
     *out = nullptr;
     if (!inst || count < 1 || count > (1 << 20)) return fail(WAVE2D_EINVAL, "need 1..2^20 instances");
-    if (flags & ~WAVE2D_BATCH_GRAPH) return fail(WAVE2D_EINVAL, "unknown batch flag bits 0x%x", flags);
+    if (flags & ~(WAVE2D_BATCH_GRAPH | WAVE2D_BATCH_ROUNDS))
+        return fail(WAVE2D_EINVAL, "unknown batch flag bits 0x%x", flags);
     wave2d_batch* b = new wave2d_batch();
     b->flags = flags;
     int r;
@@ -121,6 +308,7 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
         delete b;
         return r;
     }
+    if (const char* e = std::getenv("WAVE2D_BATCH_WAIT_MS")) b->wait_ticks = std::max(0LL, 100000LL * std::atoll(e));
     // Validate every instance and check that no two arrays of the batch overlap.
     std::vector<std::pair<const char*, size_t>> spans;
     for (int64_t i = 0; i < count; ++i) {
@@ -181,13 +369,29 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
         rc.bd = (float*)(p0 + 2 * st);
     }
 
-    // Classes: (stencil class, tuned depth, rows).
+    const size_t ni = b->inst.size();
+    b->persist = !(flags & WAVE2D_BATCH_ROUNDS) && xcc_layout_ok(b->device);
+    // Levels after the first step: full passes of the persistent kernel's
+    // depth (none in rounds mode) and a remainder run in rounds first.
+    std::vector<int64_t> left(ni), full(ni, 0);
+    for (size_t i = 0; i < ni; ++i) {
+        const int64_t lv = b->inst[i].in.steps - 1;
+        if (b->persist) {
+            const int D = persist_depth(b->inst[i].p.kind);
+            full[i] = lv / D;
+            left[i] = lv - full[i] * D;
+        } else {
+            left[i] = lv;
+        }
+    }
+
+    // Rounds classes: (stencil class, tuned depth, rows).
     struct Cls {
         int kind, depth, rows;
         std::vector<size_t> members;
     };
     std::vector<Cls> classes;
-    for (size_t i = 0; i < b->inst.size(); ++i) {
+    for (size_t i = 0; i < ni; ++i) {
         const InstRec& rc = b->inst[i];
         const wave2d_tuning tn = tuning_for(WAVE2D_F32C, rc.p.scheme, 0, 0);
         auto it = std::find_if(classes.begin(), classes.end(), [&](const Cls& c) {
@@ -200,18 +404,38 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
         it->members.push_back(i);
     }
 
-    // Rounds.
-    std::vector<int64_t> left(b->inst.size());
-    std::vector<bool> in_b(b->inst.size(), false);
-    for (size_t i = 0; i < b->inst.size(); ++i) left[i] = b->inst[i].in.steps - 1;
+    std::vector<bool> in_b(ni, false);
     std::vector<unsigned char> host;
     auto align_host = [&]() { host.resize(align256(host.size())); };
-    BatchTables gen, inr;
+    auto put = [&](const void* p, size_t n) {
+        align_host();
+        const size_t off = host.size();
+        host.insert(host.end(), (const unsigned char*)p, (const unsigned char*)p + n);
+        return off;
+    };
     int64_t lup = 0, sbytes = 0;
     for (const InstRec& rc : b->inst) {
         lup += (int64_t)(rc.p.g.nx - 2) * (rc.p.g.ny - 2) * rc.in.steps;
         sbytes += 12 * (int64_t)rc.p.g.nx * rc.p.g.ny;
     }
+
+    // First steps: one record per instance.
+    {
+        std::vector<FirstRecF32C> recs(ni);
+        std::vector<int> prefix(1, 0);
+        for (size_t i = 0; i < ni; ++i) {
+            const InstRec& rc = b->inst[i];
+            recs[i] = FirstRecF32C{rc.p.g, rc.p.kind, rc.fw, rc.in.u0, rc.in.v0, rc.in.u, rc.in.lo, rc.in.d};
+            prefix.push_back(prefix.back() + node_tiles(rc.p.g));
+        }
+        b->first_recs = put(recs.data(), recs.size() * sizeof(FirstRecF32C));
+        b->first_prefix = put(prefix.data(), prefix.size() * sizeof(int));
+        b->first_count = (int)ni;
+        b->first_blocks = prefix.back();
+    }
+
+    // Rounds of the remainder levels (all levels in rounds mode).
+    BatchTables gen, inr;
     for (;;) {
         Round rd{b->launches.size(), b->launches.size()};
         bool active = false;
@@ -246,13 +470,8 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
                     Launch L{c.kind, dep, pass == 1, 0, 0, t.count, t.prefix.back()};
                     b->st.items += t.prefix.back();
                     b->st.item_rows += (int64_t)t.prefix.back() * t.rows;
-                    align_host();
-                    L.items_off = host.size();
-                    host.insert(host.end(), t.items.begin(), t.items.end());
-                    align_host();
-                    L.prefix_off = host.size();
-                    const unsigned char* pp = (const unsigned char*)t.prefix.data();
-                    host.insert(host.end(), pp, pp + t.prefix.size() * sizeof(int));
+                    L.items_off = put(t.items.data(), t.items.size());
+                    L.prefix_off = put(t.prefix.data(), t.prefix.size() * sizeof(int));
                     b->launches.push_back(L);
                 }
                 active = true;
@@ -262,30 +481,89 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
         if (!active) break;
         b->rounds.push_back(rd);
     }
-    for (size_t i = 0; i < b->inst.size(); ++i) b->inst[i].ends_in_b = in_b[i];
-    align_host();
-    if (!host.empty()) {
-        e = hipMalloc(&b->tables, host.size());
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            (void)hipFree(b->work);
-            delete b;
-            return fail(WAVE2D_ENOMEM, "batch tables of %zu bytes: %s", host.size(), hipGetErrorString(e));
+
+    // The persistent launch: instance records, per-XCC task queues.
+    if (b->persist) {
+        b->full = full;
+        b->par0.assign(ni, 0);
+        for (size_t i = 0; i < ni; ++i) {
+            b->par0[i] = in_b[i] ? 1 : 0;
+            if (full[i] & 1) in_b[i] = !in_b[i];
         }
-        b->tables_bytes = host.size();
-        e = hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(b->tables);
+        PersistPlan pl;
+        if ((r = plan_persist(b, b->rows_cap, &pl))) {
             (void)hipFree(b->work);
             delete b;
-            return hip_fail(e, "hipMemcpy(batch tables)");
+            return r;
+        }
+        if (pl.tasks.empty()) {
+            b->persist = false;
+        } else {
+            b->p_insts = put(pl.recs.data(), pl.recs.size());
+            b->p_tasks = put(pl.tasks.data(), pl.tasks.size() * sizeof(PersistTask));
+            b->n_ctr = persist_counters((int)ni);
+            std::vector<int> zeros(b->n_ctr, 0);
+            for (int c = 0; c < kClasses; ++c) {
+                b->p_has[c] = pl.qoff[c][kPersistQueues] > pl.qoff[c][0];
+                b->p_qoff[c] = put(pl.qoff[c].data(), pl.qoff[c].size() * sizeof(int));
+                b->p_qn[c] = put(pl.qn[c].data(), pl.qn[c].size() * sizeof(int));
+                b->p_ctr[c] = put(zeros.data(), zeros.size() * sizeof(int));
+            }
+            b->st.items += pl.items;
+            b->st.item_rows += pl.item_rows;
+            b->st.persistent_items = pl.items;
+            b->p_item_rows = pl.item_rows;
+            for (size_t i = 0; i < ni; ++i) {
+                const Grid& g = b->inst[i].p.g;
+                b->st.persistent_lup += full[i] * persist_depth(b->inst[i].p.kind) * (int64_t)(g.nx - 2) * (g.ny - 2);
+                b->st.persistent_bytes += full[i] * 24 * (int64_t)g.nx * g.ny;
+            }
+            if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+                (void)hipGetLastError();
+                if (b->ev0) (void)hipEventDestroy(b->ev0);
+                (void)hipFree(b->work);
+                delete b;
+                return fail(WAVE2D_EDEVICE, "batch timing events");
+            }
         }
     }
-    int64_t copies = 0;
-    for (const InstRec& rc : b->inst) copies += rc.ends_in_b ? 1 : 0;
-    b->st.instances = (int64_t)b->inst.size();
+
+    // Copies of final states that ended in the second state: one launch.
+    {
+        std::vector<CopyRec3> recs;
+        std::vector<int> prefix(1, 0);
+        for (size_t i = 0; i < ni; ++i) {
+            InstRec& rc = b->inst[i];
+            rc.ends_in_b = in_b[i];
+            if (!rc.ends_in_b) continue;
+            recs.push_back(CopyRec3{rc.p.g, {rc.bu, rc.bl, rc.bd}, {rc.in.u, rc.in.lo, rc.in.d}});
+            prefix.push_back(prefix.back() + node_tiles(rc.p.g));
+        }
+        b->copy_recs = put(recs.data(), recs.size() * sizeof(CopyRec3));
+        b->copy_prefix = put(prefix.data(), prefix.size() * sizeof(int));
+        b->copy_count = (int)recs.size();
+        b->copy_blocks = prefix.back();
+    }
+
+    align_host();
+    e = hipMalloc(&b->tables, host.size());
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(b->work);
+        delete b;
+        return fail(WAVE2D_ENOMEM, "batch tables of %zu bytes: %s", host.size(), hipGetErrorString(e));
+    }
+    b->tables_bytes = host.size();
+    e = hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b->tables);
+        (void)hipFree(b->work);
+        delete b;
+        return hip_fail(e, "hipMemcpy(batch tables)");
+    }
+    b->st.instances = (int64_t)ni;
     b->st.rounds = (int64_t)b->rounds.size();
-    b->st.launches = (int64_t)b->inst.size() + (int64_t)b->launches.size() + copies;
+    b->st.launches = 1 + (int64_t)b->launches.size() + (b->persist ? 2 : 0) + (b->copy_count > 0 ? 1 : 0);
     b->st.lup = lup;
     b->st.state_bytes = sbytes;
     b->st.work_bytes = (int64_t)b->work_bytes;
@@ -299,9 +577,9 @@ int wave2d_batch_run(wave2d_batch* b, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const Fork* fk = nullptr;
     if (!(b->flags & WAVE2D_BATCH_GRAPH)) {
-        int rs = side_of(s, &fk);
-        if (rs) return rs;
-        return enqueue(b, s);
+        const int r = enqueue(b, s, true);
+        b->ran = b->ran || r == WAVE2D_OK;
+        return r;
     }
     if (!b->exec) {
         // The caller's stream may be the null stream, which cannot be
@@ -310,7 +588,7 @@ int wave2d_batch_run(wave2d_batch* b, void* stream)
         int rs = side_of(b->capture, &fk);  // created outside the capture
         if (rs) return rs;
         W2D_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
-        int r = enqueue(b, b->capture);
+        int r = enqueue(b, b->capture, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->capture, &g);
         if (r) {
@@ -329,6 +607,99 @@ int wave2d_batch_stats_get(const wave2d_batch* b, wave2d_batch_stats* st)
 {
     if (!b || !st) return fail(WAVE2D_EINVAL, "NULL argument");
     *st = b->st;
+    st->stalled_waits = 0;
+    if (b->persist) {
+        // Waits of the last run that gave up (the run's results are then wrong).
+        W2D_HIP(hipDeviceSynchronize());
+        int v = 0;
+        for (int c = 0; c < kClasses; ++c) {
+            if (!b->p_has[c]) continue;
+            W2D_HIP(hipMemcpy(&v, (const char*)b->tables + b->p_ctr[c] + kPersistStride * kPersistQueues * sizeof(int),
+                              sizeof(int), hipMemcpyDeviceToHost));
+            st->stalled_waits += v;
+        }
+        if (b->ran) {
+            float ms = 0.f;
+            W2D_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+            st->last_persistent_ms = ms;
+        }
+    }
+    return WAVE2D_OK;
+}
+
+int wave2d_batch_autotune(wave2d_batch* b, void* stream, int32_t* rows_cap)
+{
+    if (!b) return fail(WAVE2D_EINVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!b->persist) {
+        if (rows_cap) *rows_cap = 0;
+        return WAVE2D_OK;
+    }
+    // Time whole runs (eager launches) with each candidate height, the
+    // current one included, and keep the fastest.  The table layout does
+    // not change, so a captured graph stays valid.
+    static const int cand[] = {64, 96, 128, 160, 224, 320, 512};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    W2D_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
+    }
+    struct Release {
+        hipEvent_t a, b;
+        ~Release()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } rel{e0, e1};
+    auto upload = [&](int cap) -> int {
+        PersistPlan pl;
+        int r = plan_persist(b, cap, &pl);
+        if (r) return r;
+        char* base = (char*)b->tables;
+        W2D_HIP(hipStreamSynchronize(s));
+        W2D_HIP(hipMemcpy(base + b->p_insts, pl.recs.data(), pl.recs.size(), hipMemcpyHostToDevice));
+        W2D_HIP(hipMemcpy(base + b->p_tasks, pl.tasks.data(), pl.tasks.size() * sizeof(PersistTask),
+                          hipMemcpyHostToDevice));
+        // Queue membership follows the work model, which depends on the
+        // height: every per-class table changes with it.
+        for (int c = 0; c < kClasses; ++c) {
+            W2D_HIP(hipMemcpy(base + b->p_qoff[c], pl.qoff[c].data(), pl.qoff[c].size() * sizeof(int),
+                              hipMemcpyHostToDevice));
+            W2D_HIP(hipMemcpy(base + b->p_qn[c], pl.qn[c].data(), pl.qn[c].size() * sizeof(int), hipMemcpyHostToDevice));
+        }
+        b->st.items += pl.items - b->st.persistent_items;
+        b->st.item_rows += pl.item_rows - b->p_item_rows;
+        b->st.persistent_items = pl.items;
+        b->p_item_rows = pl.item_rows;
+        b->rows_cap = cap;
+        return WAVE2D_OK;
+    };
+    float best_ms = 1e30f;
+    int best = b->rows_cap;
+    int r;
+    for (int cap : cand) {
+        if ((r = upload(cap))) return r;
+        if ((r = enqueue(b, s, true))) return r;  // warm-up
+        float tot = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            W2D_HIP(hipEventRecord(e0, s));
+            if ((r = enqueue(b, s, true))) return r;
+            W2D_HIP(hipEventRecord(e1, s));
+            W2D_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            W2D_HIP(hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        if (tot < best_ms) {
+            best_ms = tot;
+            best = cap;
+        }
+    }
+    if ((r = upload(best))) return r;
+    b->ran = true;
+    if (rows_cap) *rows_cap = best;
     return WAVE2D_OK;
 }
 
@@ -341,6 +712,8 @@ int wave2d_batch_destroy(wave2d_batch* b)
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->tables) (void)hipFree(b->tables);
     if (b->work) (void)hipFree(b->work);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
     delete b;
     return WAVE2D_OK;
 }

@@ -63,6 +63,13 @@ void save_tune_cache(int precision, int scheme, int64_t nx, int64_t ny, const wa
 int get_device(int* dev);
 size_t align256(size_t v);
 int side_of(hipStream_t s, const Fork** out);
+// Second-state workspace bytes of a multi-step call (FP64: two grids, f32c:
+// three), each grid aligned to 256 bytes.
+size_t work_bytes_of(int precision, const Grid& g);
+// Compensated state (u, lo, d) advanced `steps` levels in place; `work`
+// (work_bytes) is the second state, or NULL for the library's own buffer.
+int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, float* lo, float* d, void* work,
+                   size_t work_bytes, hipStream_t s);
 
 }  // namespace w2d_host
 

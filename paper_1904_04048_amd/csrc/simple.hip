@@ -84,13 +84,12 @@ __global__ __launch_bounds__(BX* BY) void k_first_step(Grid g, FirstW w, const d
     u1[(size_t)j * g.ld + i] = r;
 }
 
+// First step and split at node (i, j) (inside the grid).
 template <int K>
-__global__ __launch_bounds__(BX* BY) void k_first_step_f32c(Grid g, FirstW w, const double* __restrict__ u0,
-                                                            const double* __restrict__ v0, float* __restrict__ u,
-                                                            float* __restrict__ lo, float* __restrict__ d)
+__device__ __forceinline__ void first_node_f32c(const Grid& g, const FirstW& w, const double* __restrict__ u0,
+                                                const double* __restrict__ v0, float* __restrict__ u,
+                                                float* __restrict__ lo, float* __restrict__ d, int i, int j)
 {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
     float ru = 0.f, rl = 0.f, rd = 0.f;
     if (interior(g, i, j)) {
         const Nbh<double> a = gather<K>(u0, g, i, j);
@@ -103,6 +102,69 @@ __global__ __launch_bounds__(BX* BY) void k_first_step_f32c(Grid g, FirstW w, co
     u[o] = ru;
     lo[o] = rl;
     d[o] = rd;
+}
+
+template <int K>
+__global__ __launch_bounds__(BX* BY) void k_first_step_f32c(Grid g, FirstW w, const double* __restrict__ u0,
+                                                            const double* __restrict__ v0, float* __restrict__ u,
+                                                            float* __restrict__ lo, float* __restrict__ d)
+{
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    first_node_f32c<K>(g, w, u0, v0, u, lo, d, i, j);
+}
+
+// Batched launches over many grids: record r owns the blocks
+// [prefix[r], prefix[r+1]) of a 1-D launch, one BX x BY tile of its grid
+// each (tiles numbered row by row), so every node is computed by the same
+// code as in the single-grid kernels.
+__device__ __forceinline__ int find_record(const int* __restrict__ prefix, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(BX* BY) void k_first_step_f32c_batch(const FirstRecF32C* __restrict__ recs,
+                                                                  const int* __restrict__ prefix, int count)
+{
+    const int b = (int)blockIdx.x;
+    const int r = find_record(prefix, count, b);
+    const FirstRecF32C rc = recs[r];
+    const int t = b - prefix[r];
+    const int tx = (rc.g.nx + BX - 1) / BX;
+    const int i = (t % tx) * BX + threadIdx.x, j = (t / tx) * BY + threadIdx.y;
+    if (i >= rc.g.nx || j >= rc.g.ny) return;
+    switch (rc.kind) {
+    case KIND5: first_node_f32c<KIND5>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j); break;
+    case KIND9: first_node_f32c<KIND9>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j); break;
+    default: first_node_f32c<KIND13>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j); break;
+    }
+}
+
+__global__ __launch_bounds__(BX* BY) void k_copy3_batch(const CopyRec3* __restrict__ recs,
+                                                        const int* __restrict__ prefix, int count)
+{
+    const int b = (int)blockIdx.x;
+    const int r = find_record(prefix, count, b);
+    const CopyRec3 rc = recs[r];
+    const int t = b - prefix[r];
+    const int tx = (rc.g.nx + BX - 1) / BX;
+    const int i = (t % tx) * BX + threadIdx.x, j = (t / tx) * BY + threadIdx.y;
+    if (i >= rc.g.nx || j >= rc.g.ny) return;
+    const size_t o = (size_t)j * rc.g.ld + i;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rc.dst[f][o] = rc.src[f][o];
+}
+
+__global__ void k_fill_i32(int* p, int n, int v)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < n) p[k] = v;
 }
 
 template <int K>
@@ -132,7 +194,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_f32c(Grid g, StepW32 w, const f
     if (interior(g, i, j)) {
         const Nbh<float> a = gather<K>(u, g, i, j);
         const Nbh<float> b = gather<K>(lo, g, i, j);
-        const float s = f32c_incr<K>(a, b, w.wc, w.w10, w.w11, w.w20, w.wx);
+        const float s = f32c_incr<K>(a, b, w.wc, w.w10, w.w11, w.w20, w.wx, w.wxl);
         f32c_update(s, a.C, b.C, d[o], ru, rl, rd);
     }
     u2[o] = ru;
@@ -257,6 +319,29 @@ hipError_t copy_f32x3(const Grid& g, const float* a, const float* b, const float
                       float* c2, hipStream_t s)
 {
     k_copy3<<<grid_of(g), kBlock, 0, s>>>(g, a, b, c, a2, b2, c2);
+    return hipGetLastError();
+}
+
+int node_tiles(const Grid& g) { return ((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY); }
+
+hipError_t first_step_f32c_batch(const FirstRecF32C* recs, const int* prefix, int count, int blocks, hipStream_t s)
+{
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    k_first_step_f32c_batch<<<blocks, kBlock, 0, s>>>(recs, prefix, count);
+    return hipGetLastError();
+}
+
+hipError_t copy_f32x3_batch(const CopyRec3* recs, const int* prefix, int count, int blocks, hipStream_t s)
+{
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    k_copy3_batch<<<blocks, kBlock, 0, s>>>(recs, prefix, count);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(int* p, int n, int v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<(n + 255) / 256, 256, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 

@@ -19,7 +19,9 @@
 // Per-node arithmetic is the same inline code as in the one-node-per-thread
 // kernels (point.h), so results are bit-identical to them for every DEPTH,
 // segment length and strip width.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -213,7 +215,7 @@ __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const
             eh[CW] = from_right(U[0]) - U[CW - 1];
 #pragma unroll
             for (int m = 0; m < CW; ++m) {
-                const float su = w.w10 * ((eh[m + 1] - eh[m]) + (dv[m] - cr.dv[m]));
+                const float su = mul_w2(w.wx, w.wxl, (eh[m + 1] - eh[m]) + (dv[m] - cr.dv[m]));
                 const float sl = fmaT(w.w10, cr.hs1[m] + (Wn[1][m] + Ws[1][m]), w.wc * L[m]);
                 f32c_update(su + sl, U[m], L[m], Pin[m], nv[0][m], nv[1][m], np[m]);
             }
@@ -240,7 +242,7 @@ __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const
             row_d2x(q, xq);
 #pragma unroll
             for (int m = 0; m < CW; ++m) {
-                const float s = fmaT(w.w11, xq[m], w.wx * ((xu[m] + xl[m]) + q[m]));
+                const float s = fmaT(w.w11, xq[m], mul_w2(w.wx, w.wxl, (xu[m] + xl[m]) + q[m]));
                 f32c_update(s, U[m], L[m], Pin[m], nv[0][m], nv[1][m], np[m]);
             }
         }
@@ -269,7 +271,7 @@ __device__ __forceinline__ void row_update_carry(const float (&Wc)[2][CW], const
 #pragma unroll
             for (int m = 0; m < CW; ++m) {
                 const float q = cr.q[m];
-                float s = fmaT(w.w11, xq[m], w.wx * (p[m] + q));
+                float s = fmaT(w.w11, xq[m], mul_w2(w.wx, w.wxl, p[m] + q));
                 s = fmaT(w.w20, xp[m] + ((qn[m] - q) - cr.eq[m]), s);
                 f32c_update(s, U[m], L[m], Pin[m], nv[0][m], nv[1][m], np[m]);
             }
@@ -802,9 +804,152 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const
         if (prefix[mid] <= gw) lo = mid;
         else hi = mid - 1;
     }
-    const BatchItem<Prec>& it = items[lo];
+    // A copy in registers: read through the table, the fields would be
+    // re-read from memory after every store of the pass (the compiler cannot
+    // tell the stores from the table).
+    const BatchItem<Prec> it = items[lo];
     const int wid = gw - prefix[lo];
     stream_body<Prec, K, DEPTH, CW, !INTERIOR>(it.a, it.dc, wid, it.w);
+}
+
+// ---- persistent batched passes ----------------------------------------------
+//
+// One launch per stencil class advances many compensated-FP32 instances by
+// all their full passes.  The host pins every instance to one accelerator
+// complex die (XCC, an L2 domain) and lists, per XCC, the instances' passes
+// in pass-major order as tasks of one work item per wave.  A wave reads the
+// id of the XCC it runs on, takes the next item of that XCC's queue (an
+// atomic counter) and, before running it, waits until every item of the
+// instance's previous pass is done (a per-instance counter of finished
+// items).  Items are taken in queue order, so every item a wave waits for
+// was taken earlier by a running wave, and the earliest unfinished item
+// never waits: the queue always drains.
+//
+// A finished item publishes its stores with a device-scope release fence
+// before it counts itself done (the fence waits for the stores and writes
+// this XCC's dirty L2 lines back), and an item that depends on the previous
+// pass takes a device-scope acquire fence after its wait (which invalidates
+// its CU's L1 and the L2 lines other XCCs may have changed), the pairing the
+// compiler's memory model prescribes for device-wide visibility.  Pinning
+// an instance to one XCC is for locality: the rows a pass reads were mostly
+// written through the same L2.  (Pinning with only an L1 invalidation was
+// tried and read stale rows: on one MI355X a 45^2 13-point instance whose
+// passes are one item each came out wrong at every node, run after run.)
+// Two passes apart an instance writes the state it read one pass earlier;
+// the per-pass wait orders that too (pass p+1 starts after every item of
+// pass p, the last readers of the state it overwrites, is done).
+//
+// Every wave-level decision is made by all 64 lanes on identical values
+// (atomics are issued by every lane with the increment carried by the first
+// active lane, loads of a counter by every lane), so no lane ever takes a
+// different path: a value read from one lane only (for example under
+// `lane == 0`) would let the compiler run the other lanes on into the next
+// iteration without it, where that value no longer exists.
+struct PInst {
+    SArgs<float> a[2];  // pass parity 0: state 0 -> state 1; parity 1: back
+    Decomp dc;
+    StepW32 w;
+    int kind, nb, items;
+};
+
+// The XCC the calling wave runs on (hardware register XCC_ID, low 4 bits).
+__device__ __forceinline__ int xcc_id()
+{
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((16 - 1) << 11)) & 0xf;
+}
+
+// One increment per wave: every lane executes the atomic, the first active
+// lane adds 1, the others 0; returns the counter's value before the
+// increment (wave-uniform).
+__device__ __forceinline__ int wave_fetch_inc(int* p)
+{
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int first = __builtin_amdgcn_readfirstlane(lane);
+    const int old = __hip_atomic_fetch_add(p, lane == first ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(old);
+}
+
+__device__ __forceinline__ int wave_load(const int* p)
+{
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+template <int K, int DEPTH>
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(const PInst* __restrict__ insts,
+                                                                              const PersistTask* __restrict__ tasks,
+                                                                              const int* __restrict__ qt_off,
+                                                                              const int* __restrict__ qn, int* ctr,
+                                                                              int nq, long long wait_ticks)
+{
+    const int q = __builtin_amdgcn_readfirstlane(xcc_id() % nq);
+    const int t0 = qt_off[q], t1 = qt_off[q + 1];
+    const int total = qn[q];
+    int* head = ctr + kPersistStride * q;
+    int* stalls = ctr + kPersistStride * kPersistQueues;
+    int* done = ctr + kPersistStride * (kPersistQueues + 1);
+    for (;;) {
+        const int k = wave_fetch_inc(head);
+        if (k >= total) break;
+        int lo = t0, hi = t1 - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].first <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const PersistTask t = tasks[lo];
+        int* cnt = done + kPersistStride * t.inst;
+        bool ok = true;
+        if (t.need > 0) {
+            if (wave_load(cnt) < t.need) {
+                // Poll with a growing pause (up to 64 x 512 cycles); give up
+                // after wait_ticks of the 100 MHz real-time clock, or at once
+                // when another wait of this launch has given up.
+                const long long t_start = (long long)__builtin_amdgcn_s_memrealtime();
+                int pause = 1;
+                for (int polls = 1;; ++polls) {
+                    for (int z = 0; z < pause; ++z) __builtin_amdgcn_s_sleep(8);
+                    pause = min(2 * pause, 64);
+                    if (wave_load(cnt) >= t.need) break;
+                    if ((polls & 7) == 0 && wave_load(stalls) > 0) {
+                        ok = false;
+                        break;
+                    }
+                    if ((long long)__builtin_amdgcn_s_memrealtime() - t_start > wait_ticks) {
+                        ok = false;
+                        break;
+                    }
+                }
+            }
+            // Whether or not it had to wait: caches of this CU and XCC may
+            // still hold lines of the state the previous pass rewrote.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        // A work id outside the task (tables out of step with the queue)
+        // is skipped and reported instead of being run.
+        if (ok && (k < t.first || k - t.first >= insts[t.inst].items)) ok = false;
+        if (ok) {
+            const PInst& pi = insts[t.inst];
+            const SArgs<float> a = pi.a[t.par];
+            const Decomp dc = pi.dc;
+            const StepW32 w = pi.w;
+            const int nb = pi.nb;
+            const int wid = k - t.first;
+            if (wid < nb) stream_body<PF32C, K, DEPTH, 2, true>(a, dc, wid, w);
+            else stream_body<PF32C, K, DEPTH, 2, false>(a, dc, wid - nb, w);
+        } else {
+            (void)wave_fetch_inc(stalls);
+        }
+        // The item's stores are visible device-wide before it is counted done.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        (void)wave_fetch_inc(cnt);
+    }
+}
+
+// One write of the XCC id per workgroup (the host counts the XCCs that
+// workgroups land on before it plans per-XCC queues).
+__global__ void k_xcc_probe(int* out, int n)
+{
+    if (threadIdx.x == 0 && (int)blockIdx.x < n) out[blockIdx.x] = xcc_id();
 }
 
 template <int R, int DEPTH, int CW>
@@ -1135,7 +1280,95 @@ hipError_t blaunch_prec(int kind, int depth, bool interior, const void* items, c
     }
 }
 
+// Pass depths of the persistent kernel (the single-grid defaults).
+constexpr int kPD5 = 8, kPD9 = 8, kPD13 = 6;
+
+template <int K, int DEPTH>
+int persist_inst_k(const Grid& g, const StepW32& w, int rows, float* const s0[3], float* const s1[3],
+                   unsigned char* rec, int* nb, int* rows_used)
+{
+    constexpr int R = KT<K>::R;
+    PInst p{};
+    rows = fit_rows<R, DEPTH>(g, rows, sizeof(float));
+    const Decomp dc = make_decomp<R, DEPTH, 2>(g, rows);
+    for (int par = 0; par < 2; ++par) {
+        SArgs<float>& a = p.a[par];
+        float* const* in = par ? s1 : s0;
+        float* const* out = par ? s0 : s1;
+        a.g = g;
+        a.rows = rows;
+        a.nstrips = dc.nstrips;
+        a.nwork = dc.nstrips * dc.nseg;
+        a.in_w0 = in[0];
+        a.in_w1 = in[1];
+        a.in_p = in[2];
+        a.out_w0 = out[0];
+        a.out_w1 = out[1];
+        a.out_p = out[2];
+    }
+    p.dc = dc;
+    p.w = w;
+    p.kind = K;
+    p.items = dc.nstrips * dc.nseg;
+    p.nb = p.items - dc.ns * dc.ng;
+    std::memcpy(rec, &p, sizeof p);
+    *nb = p.nb;
+    *rows_used = rows;
+    return p.items;
+}
+
+template <int K, int DEPTH>
+const void* persist_fn_k()
+{
+    return reinterpret_cast<const void*>(&k_stream_persist<K, DEPTH>);
+}
+
+const void* persist_fn(int kind)
+{
+    return kind == KIND5 ? persist_fn_k<KIND5, kPD5>() : kind == KIND9 ? persist_fn_k<KIND9, kPD9>()
+                                                                       : persist_fn_k<KIND13, kPD13>();
+}
+
 }  // namespace
+
+size_t persist_inst_size() { return sizeof(PInst); }
+
+int persist_depth(int kind) { return kind == KIND5 ? kPD5 : kind == KIND9 ? kPD9 : kPD13; }
+
+int persist_inst(const Grid& g, int kind, const StepW32& w, int rows, float* const s0[3], float* const s1[3],
+                 unsigned char* rec, int* nb, int* rows_used)
+{
+    switch (kind) {
+    case KIND5: return persist_inst_k<KIND5, kPD5>(g, w, rows, s0, s1, rec, nb, rows_used);
+    case KIND9: return persist_inst_k<KIND9, kPD9>(g, w, rows, s0, s1, rec, nb, rows_used);
+    default: return persist_inst_k<KIND13, kPD13>(g, w, rows, s0, s1, rec, nb, rows_used);
+    }
+}
+
+int persist_blocks(int kind)
+{
+    const auto f = kernel_fit(persist_fn(kind));
+    return std::max(1, f.first / kWavesPerBlock);
+}
+
+hipError_t persist_launch(int kind, const void* insts, const PersistTask* tasks, const int* qt_off, const int* qn,
+                          int* ctr, long long wait_ticks, hipStream_t s)
+{
+    const dim3 grid(persist_blocks(kind)), block(kWave * kWavesPerBlock);
+    const PInst* pi = (const PInst*)insts;
+    switch (kind) {
+    case KIND5: k_stream_persist<KIND5, kPD5><<<grid, block, 0, s>>>(pi, tasks, qt_off, qn, ctr, kPersistQueues, wait_ticks); break;
+    case KIND9: k_stream_persist<KIND9, kPD9><<<grid, block, 0, s>>>(pi, tasks, qt_off, qn, ctr, kPersistQueues, wait_ticks); break;
+    default: k_stream_persist<KIND13, kPD13><<<grid, block, 0, s>>>(pi, tasks, qt_off, qn, ctr, kPersistQueues, wait_ticks); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t xcc_probe(int* out, int n, hipStream_t s)
+{
+    k_xcc_probe<<<n, 64, 0, s>>>(out, n);
+    return hipGetLastError();
+}
 
 size_t batch_item_size(int precision)
 {

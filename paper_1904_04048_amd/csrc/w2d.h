@@ -20,9 +20,15 @@ struct StepW64 {
     double w10, w11, w20, wx;  // wx = w10 + 2 w11 + 4 w20
 };
 // wc = -4 (w10 + w11 + w20) (centre weight), wx = w10 + 2 w11 + 4 w20 (the
-// weight of Dx + Dy in the regrouped 9- and 13-point increments).
+// weight of Dx + Dy in the regrouped increments; equal to w10 for the
+// 5-point class).  wx is carried as an unevaluated sum wx + wxl of two
+// floats (wxl = the rounding error of wx): a weight rounded to single
+// precision changes the scheme's frequencies by up to 3e-8 relative, a phase
+// error that grows with the step count (about 1.4e-5 of max|u| after 5000
+// steps on a 64^2 grid).  The other weights multiply higher differences,
+// whose share of the increment is smaller by lambda^2 theta^2 / 6 or less.
 struct StepW32 {
-    float w10, w11, w20, wc, wx;
+    float w10, w11, w20, wc, wx, wxl;
 };
 // First-step weights: A node weights and B node weights divided by tau.
 struct FirstW {
@@ -48,6 +54,27 @@ hipError_t copy_f32x3(const Grid& g, const float* a, const float* b, const float
                       float* c2, hipStream_t s);
 hipError_t copy_f64x2(const Grid& g, const double* a, const double* b, double* a2, double* b2, hipStream_t s);
 hipError_t swap_f64(const Grid& g, double* a, double* b, hipStream_t s);
+// Batched one-node-per-thread launches over many grids: record r owns the
+// blocks [prefix[r], prefix[r+1]) of one launch of `blocks` blocks
+// (node_tiles(g) blocks per grid).
+struct FirstRecF32C {
+    Grid g;
+    int kind;
+    FirstW w;
+    const double* u0;
+    const double* v0;
+    float *u, *lo, *d;
+};
+struct CopyRec3 {
+    Grid g;
+    const float* src[3];
+    float* dst[3];
+};
+int node_tiles(const Grid& g);
+hipError_t first_step_f32c_batch(const FirstRecF32C* recs, const int* prefix, int count, int blocks, hipStream_t s);
+hipError_t copy_f32x3_batch(const CopyRec3* recs, const int* prefix, int count, int blocks, hipStream_t s);
+// p[0..n) = v (a kernel, so that it can be captured in a graph).
+hipError_t fill_i32(int* p, int n, int v, hipStream_t s);
 // b <- a on interior nodes, 0 on the boundary.
 hipError_t copy_interior_f64(const Grid& g, const double* a, double* b, hipStream_t s);
 
@@ -116,6 +143,40 @@ struct ShapeFit {
     int halo_rows;   // rows a pass reaches beyond its outputs (R x depth)
 };
 ShapeFit stream_shape_fit(int precision, int kind, int depth);
+
+// ---- persistent batched passes (stream.hip) --------------------------------
+// One launch runs all passes of many compensated instances: one work queue
+// per XCC (instances pinned to one XCC), tasks of one item per wave.
+constexpr int kPersistQueues = 8;
+// Counters of a persistent launch, one per 128-byte line (kPersistStride
+// ints apart): queue heads 0..7, then the count of waits that gave up, then
+// the finished items of each instance.  All zero before the launch.
+constexpr int kPersistStride = 32;
+inline int persist_counters(int instances) { return kPersistStride * (kPersistQueues + 1 + instances); }
+// Items [first, first + items) of a queue: pass `par` parity of instance
+// `inst`, runnable once `need` items of the instance are done.
+struct PersistTask {
+    int inst, par, need, first;
+};
+size_t persist_inst_size();
+// Pass depth of the persistent kernel for a stencil class.
+int persist_depth(int kind);
+// Write the device record of one instance into rec (persist_inst_size()
+// bytes): grid, class, weights, states s0 (u, lo, d) and s1 (the second
+// state), segment height `rows` (clamped like single-grid passes).  Returns
+// its work items per pass; *nb = how many of them are boundary items,
+// *rows_used = the height applied.
+int persist_inst(const Grid& g, int kind, const StepW32& w, int rows, float* const s0[3], float* const s1[3],
+                 unsigned char* rec, int* nb, int* rows_used);
+// Workgroups of one persistent launch of a class (the kernel's resident
+// capacity).
+int persist_blocks(int kind);
+// All queued passes of one stencil class's instances; a wait gives up after
+// wait_ticks of the 100 MHz real-time clock.
+hipError_t persist_launch(int kind, const void* insts, const PersistTask* tasks, const int* qt_off, const int* qn,
+                          int* ctr, long long wait_ticks, hipStream_t s);
+// XCC id of each of n workgroups (out[k], device).
+hipError_t xcc_probe(int* out, int n, hipStream_t s);
 
 // ---- reductions (norms.hip) -------------------------------------------------
 // Partial sums into `part` (nblk x 4 doubles), then a single-block final

@@ -148,3 +148,102 @@ def test_autotune_picks_supported_shape_and_keeps_results(prec, scheme):
             assert all(torch.equal(a[k], a[k + 3]) for k in range(3))
     finally:
         w.wave2d_set_tuning(prec, scheme)
+
+
+# Instances with enough levels that most passes run in the persistent
+# launch (full passes of 8 levels, 6 for 13 points), plus remainders.
+PCASES = [(nx, ny, (w.P5, w.P9, w.P13, w.C9)[k % 4], st, w.FIRST_CONVENTIONAL if k % 4 == 3 else 0, fr)
+          for k, (nx, ny, st, fr) in enumerate([
+              (64, 64, 101, 0.9), (640, 517, 77, 0.8), (129, 700, 150, 0.9), (300, 300, 64, 0.5),
+              (97, 65, 203, 0.95), (1025, 257, 49, 0.9), (513, 513, 90, 0.7), (66, 1100, 31, 0.9),
+              (200, 130, 121, 0.6), (777, 333, 58, 0.9), (45, 45, 300, 0.9), (1100, 90, 40, 0.85)])]
+
+
+def _clear(insts):
+    for t in insts:
+        t["u"].fill_(float("nan"))
+        t["lo"].fill_(float("nan"))
+        t["d"].fill_(float("nan"))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_persistent_batch_bitwise_equals_rounds_and_solo(graph):
+    insts = _make(PCASES, seed=40)
+    refs = [_solo(t) for t in insts]
+    bp = w.wave2d_batch_create(insts, w.BATCH_GRAPH if graph else 0)
+    br = w.wave2d_batch_create(insts, w.BATCH_ROUNDS)
+    try:
+        sp = w.wave2d_batch_stats_get(bp)
+        sr = w.wave2d_batch_stats_get(br)
+        print(f"persistent: {sp}\nrounds: {sr}", flush=True)
+        assert sp["persistent_items"] > 0 and sr["persistent_items"] == 0
+        assert sp["launches"] < sr["launches"] and sp["lup"] == sr["lup"]
+        for rep in range(3 if graph else 1):
+            _clear(insts)
+            w.wave2d_batch_run(bp)
+            torch.cuda.synchronize()
+            assert w.wave2d_batch_stats_get(bp)["stalled_waits"] == 0
+            for k, (t, (u, lo, d)) in enumerate(zip(insts, refs)):
+                assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (rep, k)
+            x = torch.randn(1000, 1000, device="cuda")
+            (x @ x).sum().item()
+        _clear(insts)
+        w.wave2d_batch_run(br)
+        torch.cuda.synchronize()
+        for k, (t, (u, lo, d)) in enumerate(zip(insts, refs)):
+            assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), k
+    finally:
+        w.wave2d_batch_destroy(bp)
+        w.wave2d_batch_destroy(br)
+
+
+def test_persistent_batch_wait_limit_ends_the_launch(monkeypatch):
+    # A wait limit of zero polls (set from the host) makes items whose
+    # previous pass is still running give up: the launch must still end,
+    # and the batch must report the stalled waits.
+    insts = _make([(1025, 1025, w.P9, 50, 0, 0.9)], seed=50)
+    monkeypatch.setenv("WAVE2D_BATCH_WAIT_MS", "0")
+    b = w.wave2d_batch_create(insts)
+    monkeypatch.delenv("WAVE2D_BATCH_WAIT_MS")
+    try:
+        assert w.wave2d_batch_stats_get(b)["persistent_items"] > 0
+        w.wave2d_batch_run(b)
+        torch.cuda.synchronize()
+        assert w.wave2d_batch_stats_get(b)["stalled_waits"] > 0
+    finally:
+        w.wave2d_batch_destroy(b)
+    # A batch created afterwards uses the normal limit and is exact.
+    b = w.wave2d_batch_create(insts)
+    try:
+        _clear(insts)
+        w.wave2d_batch_run(b)
+        torch.cuda.synchronize()
+        assert w.wave2d_batch_stats_get(b)["stalled_waits"] == 0
+    finally:
+        w.wave2d_batch_destroy(b)
+    u, lo, d = _solo(insts[0])
+    assert torch.equal(insts[0]["u"], u) and torch.equal(insts[0]["lo"], lo) and torch.equal(insts[0]["d"], d)
+
+
+def test_persistent_batch_autotune_keeps_results():
+    # Autotuning re-plans the persistent tables for each candidate segment
+    # height (queue membership follows the work model, so every per-queue
+    # table changes); the batch must stay exact after it, eager and replayed.
+    insts = _make(PCASES, seed=60)
+    refs = [_solo(t) for t in insts]
+    b = w.wave2d_batch_create(insts, w.BATCH_GRAPH)
+    try:
+        cap = w.wave2d_batch_autotune(b)
+        assert cap in (64, 96, 128, 160, 224, 320, 512)
+        st = w.wave2d_batch_stats_get(b)
+        assert st["stalled_waits"] == 0 and st["last_persistent_ms"] > 0
+        for rep in range(2):
+            _clear(insts)
+            w.wave2d_batch_run(b)
+            torch.cuda.synchronize()
+            assert w.wave2d_batch_stats_get(b)["stalled_waits"] == 0
+            for k, (t, (u, lo, d)) in enumerate(zip(insts, refs)):
+                assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (rep, k)
+    finally:
+        w.wave2d_batch_destroy(b)

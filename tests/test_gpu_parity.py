@@ -292,3 +292,47 @@ def test_stability_limit_is_accepted_and_beyond_rejected():
             w.wave2d_run(U0, U0.clone(), P, C, h, lam * 1.001 * h, 1.0, s, 3, _flags_for(s, False))
         w.wave2d_run(U0, U0.clone(), P, C, h, lam * 1.001 * h, 1.0, s, 3,
                      _flags_for(s, False) | w.ALLOW_UNSTABLE)
+
+
+def _worst_rounding_lambda(scheme, lo=0.85, hi=0.9, n=2001):
+    """Courant fraction in [lo, hi] x lambda_max whose two-step weight of
+    Dx + Dy (lambda^2 (a10 + 2 a11 + 4 a20), Sec. 6 brackets) loses the most
+    relative precision when rounded to single precision."""
+    lmax = oracle.lambda_max(scheme)
+    best, bf = None, -1.0
+    for f in np.linspace(lo, hi, n):
+        lam = f * lmax
+        a, _, _ = oracle.brackets(scheme, lam)
+        wx = lam * lam * (a[0] + 2 * a[1] + 4 * a[2])
+        e = abs(float(np.float32(wx)) - wx) / wx
+        if e > bf:
+            best, bf = f, e
+    return best, bf
+
+
+@pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
+@pytest.mark.parametrize("n,steps,seed", [(64, 5000, 11), (64, 5000, 12), (129, 5000, 13)])
+def test_f32c_long_coarse_run(scheme, n, steps, seed):
+    """Coarse grids over thousands of steps (the small, long instances of
+    the batched and served workloads): a single-precision weight would
+    shift every mode's frequency and the phase error would grow with the
+    step count; the compensated path stays within 1e-5 of max|u| against
+    the FP64 oracle after the full run, at the Courant number whose weight
+    rounds worst."""
+    frac, rounding = _worst_rounding_lambda(scheme)
+    assert rounding > 2.5e-8  # a badly rounding weight was found
+    (u0, v0), _ = smooth_data(n, n, seed)
+    h = 1.0 / (n - 1)
+    tau = frac * w.wave2d_lambda_max(scheme) * h
+    _, rc = oracle.run(u0, v0, h, tau, 1.0, scheme, steps)
+    U0, V0 = dev_grid(u0), dev_grid(v0)
+    u = torch.full(U0.shape, float("nan"), dtype=torch.float32, device=U0.device)
+    lo, d = torch.full_like(u, float("nan")), torch.full_like(u, float("nan"))
+    w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, scheme, steps)
+    out = torch.full_like(U0, float("nan"))
+    w.wave2d_f32c_export(u, lo, out)
+    got = out.cpu().numpy()
+    assert np.isfinite(got).all()
+    err = oracle.rel_max_err(got, rc)
+    print(f"scheme {scheme} n {n} steps {steps} lambda {frac:.5f} x max: rel err {err:.3e}")
+    assert err <= TOL32, err
