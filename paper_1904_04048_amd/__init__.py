@@ -16,14 +16,14 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, BATCH_ROUNDS, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, P5,
+from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, BATCH_ROUNDS, C9, F32C, F64, FIRST_CONVENTIONAL, KERNEL_SIMPLE, NOALLOC_MAX_BYTES, P5,
                    P9, P13, PERIODIC, BatchStats, Instance, Request, Result, ServerStats, Tuning, Wave2dError)
 
 __all__ = [
     "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE", "PERIODIC",
     "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_work_bytes", "wave2d_first_step",
-    "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step",
-    "wave2d_f32c_export",
+    "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_step_noalloc",
+    "NOALLOC_MAX_BYTES", "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
     "wave2d_release", "wave2d_autotune", "wave2d_batch_create", "wave2d_batch_run", "wave2d_batch_stats_get", "wave2d_batch_autotune",
     "wave2d_batch_destroy", "BATCH_GRAPH", "BATCH_ROUNDS", "wave2d_sine_series", "wave2d_server_create", "wave2d_server_submit",
@@ -131,6 +131,15 @@ def wave2d_f32c_step(u, lo, d, h, tau, c, scheme, steps, flags=0, work=None):
     wp, wb = _work(work)
     _lib.check(_lib.load().wave2d_f32c_step(nx, ny, ld, h, tau, c, scheme, flags, steps, _p(u), _p(lo), _p(d),
                                             wp, wb, s))
+
+
+def wave2d_f32c_step_noalloc(u, lo, d, h, tau, c, scheme, steps, flags=0):
+    """wave2d_f32c_step with the second state in the library's fixed device
+    array (no allocation; grids up to NOALLOC_MAX_BYTES of workspace)."""
+    import torch
+    nx, ny, ld, s = _grid(u, lo, d, dtypes=(torch.float32,) * 3)
+    _lib.check(_lib.load().wave2d_f32c_step_noalloc(nx, ny, ld, h, tau, c, scheme, flags, steps, _p(u), _p(lo),
+                                                    _p(d), s))
 
 
 def wave2d_f32c_export(u, lo, out):

@@ -14,6 +14,7 @@ ALLOW_UNSTABLE = 0x2
 PERIODIC = 0x4
 KERNEL_SIMPLE = 0x100
 F64, F32C = 0, 1
+NOALLOC_MAX_BYTES = 64 << 20  # WAVE2D_NOALLOC_MAX_BYTES
 
 I64 = ctypes.c_int64
 D = ctypes.c_double
@@ -77,6 +78,7 @@ _SIGS = {
     "wave2d_run": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P, P, SZ, P]),
     "wave2d_f32c_init": (I, [I64, I64, I64, P, P, P, P, P, P]),
     "wave2d_f32c_step": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P, SZ, P]),
+    "wave2d_f32c_step_noalloc": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P]),
     "wave2d_f32c_export": (I, [I64, I64, I64, P, P, P, P]),
     "wave2d_f32c_run": (I, [I64, I64, I64, D, D, D, I, U32, I64, P, P, P, P, P, P, SZ, P]),
     "wave2d_norms": (I, [I64, I64, I64, P, P, P, P]),
