@@ -825,16 +825,22 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const
 // was taken earlier by a running wave, and the earliest unfinished item
 // never waits: the queue always drains.
 //
-// A finished item publishes its stores with a device-scope release fence
-// before it counts itself done (the fence waits for the stores and writes
-// this XCC's dirty L2 lines back), and an item that depends on the previous
-// pass takes a device-scope acquire fence after its wait (which invalidates
-// its CU's L1 and the L2 lines other XCCs may have changed), the pairing the
-// compiler's memory model prescribes for device-wide visibility.  Pinning
-// an instance to one XCC is for locality: the rows a pass reads were mostly
-// written through the same L2.  (Pinning with only an L1 invalidation was
-// tried and read stale rows: on one MI355X a 45^2 13-point instance whose
-// passes are one item each came out wrong at every node, run after run.)
+// Every item of an instance runs on the one XCC its queue belongs to, so
+// all of an instance's traffic inside the launch goes through one L2, the
+// coherence point of that XCC's CUs; only the CUs' L1 caches (write-through)
+// can hold stale lines.  A finished item therefore waits until its stores
+// have reached L2 (s_waitcnt on all counters) before it counts itself done,
+// and an item that depends on the previous pass invalidates its CU's L1
+// (buffer_inv sc1, the device-scope acquire fence) after its wait.  No L2
+// write-back is needed inside the launch (kernel boundaries write L2 back
+// and invalidate it, which covers the launches before and after).  Two
+// alternatives were measured on one MI355X over the 512-instance batch,
+// bitwise against the batch run as rounds of ordinary launches: the
+// device-scope release fence (buffer_wbl2 sc1, a write-back of the XCC's
+// dirty L2 lines per item) was exact but 1.46x slower in total; a
+// workgroup-scope invalidation (buffer_inv sc0) instead of sc1 leaves the
+// L1 stale and got about 20 instances wrong per run, as did dropping the
+// invalidation.
 // Two passes apart an instance writes the state it read one pass earlier;
 // the per-pass wait orders that too (pass p+1 starts after every item of
 // pass p, the last readers of the state it overwrites, is done).
@@ -920,8 +926,8 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
                     }
                 }
             }
-            // Whether or not it had to wait: caches of this CU and XCC may
-            // still hold lines of the state the previous pass rewrote.
+            // Whether or not it had to wait: this CU's L1 may still hold
+            // lines of the state the previous pass rewrote.
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         // A work id outside the task (tables out of step with the queue)
@@ -939,8 +945,10 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
         } else {
             (void)wave_fetch_inc(stalls);
         }
-        // The item's stores are visible device-wide before it is counted done.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // The item's loads are done and its stores are in this XCC's L2
+        // before it is counted done (the memory clobber keeps the compiler
+        // from moving memory operations across the wait).
+        asm volatile("s_waitcnt vmcnt(0) expcnt(0) lgkmcnt(0)" ::: "memory");
         (void)wave_fetch_inc(cnt);
     }
 }
