@@ -91,7 +91,13 @@ struct wave2d_batch {
     bool p_has[kClasses] = {};
     int n_ctr = 0;
     long long wait_ticks = kWaitTicks;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the persistent launch
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the persistent launches
+    // The stencil classes' persistent launches run concurrently: the first
+    // on the caller's stream, the others on two private streams forked from
+    // it and joined back (a class that runs out of work leaves its CUs to
+    // the others instead of idling through the tail of its queues).
+    hipStream_t p_side[kClasses - 1] = {};
+    hipEvent_t p_fork = nullptr, p_join[kClasses - 1] = {};
     bool ran = false;
     // Persistent plan inputs: full passes and the parity of the first one
     // per instance, and the tallest segment of a work item.
@@ -102,6 +108,18 @@ struct wave2d_batch {
 };
 
 namespace {
+
+void release_streams(wave2d_batch* b)
+{
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->p_fork) (void)hipEventDestroy(b->p_fork);
+    for (int k = 0; k < kClasses - 1; ++k) {
+        if (b->p_join[k]) (void)hipEventDestroy(b->p_join[k]);
+        if (b->p_side[k]) (void)hipStreamDestroy(b->p_side[k]);
+    }
+    b->ev0 = b->ev1 = b->p_fork = nullptr;
+}
 
 int largest_supported(int d)
 {
@@ -278,11 +296,22 @@ int enqueue(wave2d_batch* b, hipStream_t s, bool timing)
     }
     if (b->persist) {
         if (timing) W2D_HIP(hipEventRecord(b->ev0, s));
-        for (int c = kClasses - 1; c >= 0; --c)
-            if (b->p_has[c])
-                W2D_HIP(persist_launch(c, base + b->p_insts, (const PersistTask*)(base + b->p_tasks),
-                                       (const int*)(base + b->p_qoff[c]), (const int*)(base + b->p_qn[c]),
-                                       (int*)(base + b->p_ctr[c]), b->wait_ticks, s));
+        W2D_HIP(hipEventRecord(b->p_fork, s));
+        int used = 0;
+        for (int c = kClasses - 1; c >= 0; --c) {
+            if (!b->p_has[c]) continue;
+            hipStream_t sc = s;
+            if (used > 0) {
+                sc = b->p_side[used - 1];
+                W2D_HIP(hipStreamWaitEvent(sc, b->p_fork, 0));
+            }
+            W2D_HIP(persist_launch(c, base + b->p_insts, (const PersistTask*)(base + b->p_tasks),
+                                   (const int*)(base + b->p_qoff[c]), (const int*)(base + b->p_qn[c]),
+                                   (int*)(base + b->p_ctr[c]), b->wait_ticks, sc));
+            if (used > 0) W2D_HIP(hipEventRecord(b->p_join[used - 1], sc));
+            ++used;
+        }
+        for (int k = 0; k + 1 < used; ++k) W2D_HIP(hipStreamWaitEvent(s, b->p_join[k], 0));
         if (timing) W2D_HIP(hipEventRecord(b->ev1, s));
     }
     W2D_HIP(copy_f32x3_batch((const CopyRec3*)(base + b->copy_recs), (const int*)(base + b->copy_prefix),
@@ -518,12 +547,17 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
                 b->st.persistent_lup += full[i] * persist_depth(b->inst[i].p.kind) * (int64_t)(g.nx - 2) * (g.ny - 2);
                 b->st.persistent_bytes += full[i] * 24 * (int64_t)g.nx * g.ny;
             }
-            if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+            bool ok = hipEventCreate(&b->ev0) == hipSuccess && hipEventCreate(&b->ev1) == hipSuccess &&
+                      hipEventCreateWithFlags(&b->p_fork, hipEventDisableTiming) == hipSuccess;
+            for (int k = 0; ok && k < kClasses - 1; ++k)
+                ok = hipStreamCreateWithFlags(&b->p_side[k], hipStreamNonBlocking) == hipSuccess &&
+                     hipEventCreateWithFlags(&b->p_join[k], hipEventDisableTiming) == hipSuccess;
+            if (!ok) {
                 (void)hipGetLastError();
-                if (b->ev0) (void)hipEventDestroy(b->ev0);
+                release_streams(b);
                 (void)hipFree(b->work);
                 delete b;
-                return fail(WAVE2D_EDEVICE, "batch timing events");
+                return fail(WAVE2D_EDEVICE, "batch streams and events");
             }
         }
     }
@@ -549,6 +583,7 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
     e = hipMalloc(&b->tables, host.size());
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        release_streams(b);
         (void)hipFree(b->work);
         delete b;
         return fail(WAVE2D_ENOMEM, "batch tables of %zu bytes: %s", host.size(), hipGetErrorString(e));
@@ -556,6 +591,7 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
     b->tables_bytes = host.size();
     e = hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
+        release_streams(b);
         (void)hipFree(b->tables);
         (void)hipFree(b->work);
         delete b;
@@ -712,8 +748,7 @@ int wave2d_batch_destroy(wave2d_batch* b)
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->tables) (void)hipFree(b->tables);
     if (b->work) (void)hipFree(b->work);
-    if (b->ev0) (void)hipEventDestroy(b->ev0);
-    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    release_streams(b);
     delete b;
     return WAVE2D_OK;
 }
