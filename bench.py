@@ -121,7 +121,10 @@ def alu_view(path):
 
 # ---- the batched workload (headline) ---------------------------------------------
 
-def make_batch(dev, flags=0):
+def make_batch(dev, flags=0, host_data=False):
+    """The 512 instances and their batch.  host_data: sample the initial data
+    on the host and copy it over (no device kernels: the counter-collection
+    runs keep their dispatch count small)."""
     import torch
 
     import paper_1904_04048_amd as w
@@ -129,7 +132,11 @@ def make_batch(dev, flags=0):
     probs = W.c4()
     insts = []
     for pr in probs:
-        U0, V0 = W.sine_series_torch(pr.nx, pr.ny, pr.modes, dev)
+        if host_data:
+            u0, v0 = W.sine_series_matmul(pr.nx, pr.ny, pr.modes)
+            U0, V0 = torch.from_numpy(u0).to(dev), torch.from_numpy(v0).to(dev)
+        else:
+            U0, V0 = W.sine_series_torch(pr.nx, pr.ny, pr.modes, dev)
         u = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device=dev)
         insts.append(dict(nx=pr.nx, ny=pr.ny, h=pr.h, tau=pr.tau, c=pr.c, scheme=pr.scheme, steps=pr.steps,
                           flags=0, u0=U0, v0=V0, u=u, lo=torch.empty_like(u), d=torch.empty_like(u)))
@@ -198,6 +205,7 @@ def batch_bench(args, dev):
     # The same batch replayed as one captured graph (not timed per launch).
     bg = w.wave2d_batch_create(insts, w.BATCH_GRAPH)
     try:
+        w.wave2d_batch_set_rows_cap(bg, cap)
         w.wave2d_batch_run(bg)
         torch.cuda.synchronize()
         reps = max(2, min(5, args.steps))
@@ -209,10 +217,13 @@ def batch_bench(args, dev):
     finally:
         w.wave2d_batch_destroy(bg)
     t_launch = sum(ms_persist) / len(ms_persist) / 1e3
-    cfg = {"kernel": "k_stream_persist", "rows_cap": cap, "source": kernel_source_hash()}
+    cfg = {"kernel": "k_stream_persist", "source": kernel_source_hash()}
+    crec = counter_record(BATCH_COUNTERS) or {}
     roof = roofline_hbm(st["persistent_bytes"], t_launch, st["persistent_lup"], traffic_record(BATCH_COUNTERS, cfg),
-                        "k_stream_persist (every full pass of all 512 instances, one launch per step)",
+                        "k_stream_persist (every full pass of all 512 instances: three concurrent per-class "
+                        "launches per step, timed together)",
                         {"pass_depths": {"5": 8, "9": 8, "13": 6}, "rows_cap": cap,
+                         "traffic_rows_cap": crec.get("rows_cap") if crec.get("kernel_cfg") == cfg else None,
                          "launches_timed": len(ms_persist), "alu": alu_view(BATCH_COUNTERS)})
     return {"value": round(st["lup"] * args.steps / elapsed / 1e9, 2),
             "ms_per_step": round(elapsed / args.steps * 1e3, 3), "graph_replay_value": round(graph_glups, 2),
@@ -586,7 +597,7 @@ def profile_run(dev):
     for _ in range(3):
         b.copy_(a)
     del a, b
-    probs, insts, bt = make_batch(dev)
+    probs, insts, bt = make_batch(dev, host_data=True)
     try:
         cap = w.wave2d_batch_autotune(bt)
         w.wave2d_batch_run(bt)
@@ -646,40 +657,52 @@ def summarize(prof_dir):
     assert rec["source"] == kernel_source_hash(), "profiles were taken on other kernel sources"
 
     def per_kernel(path, multi=False):
+        """(dispatch id, value) lists per kernel name (and counter name)."""
         out = {}
         if not os.path.exists(path):
             return out
         for r in csv.DictReader(open(path)):
             key = (r["Kernel_Name"], r["Counter_Name"]) if multi else r["Kernel_Name"]
-            out.setdefault(key, []).append(float(r["Counter_Value"]))
+            out.setdefault(key, []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
         return out
+
+    def pick(vals, how):
+        """The median over a kernel's dispatches, or its last dispatch."""
+        return statistics.median(v for _, v in vals) if how == "median" else max(vals)[1]
 
     fetch = per_kernel(os.path.join(prof_dir, "pmc_fetch", "fetch_counter_collection.csv"))
     write = per_kernel(os.path.join(prof_dir, "pmc_write", "write_counter_collection.csv"))
     sq = per_kernel(os.path.join(prof_dir, "pmc_sq", "sq_counter_collection.csv"), True)
     gr = per_kernel(os.path.join(prof_dir, "pmc_grbm", "grbm_counter_collection.csv"), True)
     copy_bytes = 256 * 1024 * 1024
-    cf = [v for k, v in fetch.items() if "copyBuffer" in k][0]
-    cw = [v for k, v in write.items() if "copyBuffer" in k][0]
-    f_scale = copy_bytes / (statistics.median(cf) * 1024)
-    w_scale = copy_bytes / (statistics.median(cw) * 1024)
+    # The calibration copies are the three largest copy-kernel dispatches
+    # (host-to-device uploads of the batch's data also run as copy kernels).
+    cf = statistics.median(sorted(v for _, v in [v for k, v in fetch.items() if "copyBuffer" in k][0])[-3:])
+    cw = statistics.median(sorted(v for _, v in [v for k, v in write.items() if "copyBuffer" in k][0])[-3:])
+    f_scale = copy_bytes / (cf * 1024)
+    w_scale = copy_bytes / (cw * 1024)
     simds = 256 * 4
 
-    def one(title, path, match, cfg, alg, lup):
-        kf = [statistics.median(v) for k, v in fetch.items() if match(k)]
-        kw = [statistics.median(v) for k, v in write.items() if match(k)]
-        assert len(kf) == 1 and len(kw) == 1, (title, len(kf), len(kw))
-        rd = kf[0] * 1024 * f_scale
-        wr = kw[0] * 1024 * w_scale
-        out = {"kernel_cfg": cfg, "hbm_bytes_per_launch": int(rd + wr), "read_bytes_per_launch": int(rd),
+    def one(title, path, match, cfg, alg, lup, how="median", nk=1, note="", extra=None):
+        """Counters of one launch of a kernel, or summed over the `nk`
+        kernels that `match` selects (the batch's per-class launches)."""
+        extra = extra or {}
+        kf = [pick(v, how) for k, v in fetch.items() if match(k)]
+        kw = [pick(v, how) for k, v in write.items() if match(k)]
+        assert len(kf) == nk and len(kw) == nk, (title, len(kf), len(kw))
+        rd = sum(kf) * 1024 * f_scale
+        wr = sum(kw) * 1024 * w_scale
+        out = {"kernel_cfg": cfg, **extra, "hbm_bytes_per_launch": int(rd + wr), "read_bytes_per_launch": int(rd),
                "write_bytes_per_launch": int(wr), "algorithmic_bytes_per_launch": int(alg),
                "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)}
         issue_md = []
-        v = {c: [statistics.median(x) for (k, cn), x in sq.items() if match(k) and cn == c]
+        v = {c: [pick(x, how) for (k, cn), x in sq.items() if match(k) and cn == c]
              for c in ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_WAIT_INST_ANY",
                        "SQ_WAVE_CYCLES")}
-        g = [statistics.median(x) for (k, cn), x in gr.items() if match(k) and cn == "GRBM_GUI_ACTIVE"]
-        if all(len(x) == 1 for x in v.values()) and len(g) == 1:
+        g = [pick(x, how) for (k, cn), x in gr.items() if match(k) and cn == "GRBM_GUI_ACTIVE"]
+        if all(len(x) == nk for x in v.values()) and len(g) == nk:
+            v = {c: [sum(x)] for c, x in v.items()}
+            g = [sum(g)]
             cycles = g[0] / XCDS  # the counter sums the 8 XCDs' clocks
             valu = v["SQ_INSTS_VALU"][0]
             issue = valu * 4 / (simds * cycles)
@@ -699,21 +722,23 @@ def summarize(prof_dir):
                         "updates of the launch (useful updates only)."]
         md = [f"# {title}", "", "Commands (from the repository root, one MI355X, one counter group per run):", ""] + \
             PROFILE_CMDS + ["",
-                            f"Copy calibration (256 MiB device copy): FETCH_SIZE reads {statistics.median(cf):.0f} "
-                            f"KiB (scale {f_scale:.3f}), WRITE_SIZE reads {statistics.median(cw):.0f} KiB "
+                            f"Copy calibration (256 MiB device copy): FETCH_SIZE reads {cf:.0f} "
+                            f"KiB (scale {f_scale:.3f}), WRITE_SIZE reads {cw:.0f} KiB "
                             f"(scale {w_scale:.3f}).", "",
-                            f"One launch: FETCH_SIZE {kf[0]:.0f} KiB, WRITE_SIZE {kw[0]:.0f} KiB; scaled: read "
-                            f"{rd / 1e6:.1f} MB, write {wr / 1e6:.1f} MB against {alg / 1e6:.1f} MB algorithmic "
-                            f"({(rd + wr) / alg:.2f}x)."] + issue_md + \
+                            f"One launch{note}: FETCH_SIZE {sum(kf):.0f} KiB, WRITE_SIZE {sum(kw):.0f} KiB; "
+                            f"scaled: read {rd / 1e6:.1f} MB, write {wr / 1e6:.1f} MB against {alg / 1e6:.1f} MB "
+                            f"algorithmic ({(rd + wr) / alg:.2f}x)."] + issue_md + \
             ["", "```json", json.dumps(out, indent=1), "```", ""]
         open(path, "w").write("\n".join(md))
         print(title, json.dumps(out))
 
     bst = rec["batch"]
-    one("HBM traffic and issue of the persistent batch launch (512 instances, compensated FP32)",
+    one("HBM traffic and issue of the persistent batch launches (512 instances, compensated FP32)",
         BATCH_COUNTERS, lambda k: "k_stream_persist" in k,
-        {"kernel": "k_stream_persist", "rows_cap": rec["rows_cap"], "source": rec["source"]},
-        bst["persistent_bytes"], bst["persistent_lup"])
+        {"kernel": "k_stream_persist", "source": rec["source"]},
+        bst["persistent_bytes"], bst["persistent_lup"], how="last", nk=3, extra={"rows_cap": rec["rows_cap"]},
+        note=(f" (the three per-class launches of the run after autotuning, segments of at most "
+              f"{rec['rows_cap']} rows, summed; under counter collection the launches run one at a time)"))
     for scheme, path, kind, p in ((9, C2_COUNTERS, 1, W.c2()), (13, C3_COUNTERS, 2, W.c3())):
         sh = rec["shapes"][str(scheme)]
         tag = f"PF32C, {kind}, {sh['depth']}, 2>"
@@ -730,7 +755,8 @@ def summarize(prof_dir):
         lines = ["# Kernel statistics of a benchmark run (batch headline and single grids)", "",
                  "Command (from the repository root, on one MI355X):", "",
                  "    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_bench -o bench \\",
-                 "        -- python3 bench.py --steps 3 --warmup 1 --no-cpu --no-serve", "",
+                 "        -- python3 bench.py --steps 3 --warmup 1 --no-cpu --no-serve > gpurun_out/prof_bench.log",
+                 "",
                  "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
         for r in stats[:14]:
             name = r["Name"].replace("w2d::(anonymous namespace)::", "").replace("|", "/")
@@ -738,8 +764,45 @@ def summarize(prof_dir):
                 name = name[:90] + "..."
             lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
                          f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} | {float(r['Percentage']):.1f} |")
+        lines += batch_spans(prof_dir)
         open(BATCH_STATS, "w").write("\n".join(lines) + "\n")
         print(open(BATCH_STATS).read())
+
+
+AUTOTUNE_RUNS = 7 * 3  # wave2d_batch_autotune: 7 candidate heights x (1 warm-up + 2 timed runs)
+
+
+def batch_spans(prof_dir):
+    """The persistent phase of each batch run in the kernel trace: from the
+    first start to the last end of its three concurrent per-class launches.
+    Runs in trace order: autotuning, warm-up, the timed steps, then the
+    graph replays; the timed steps' mean is set beside the bench line's own
+    HIP-event figure of the same run."""
+    import csv
+    import statistics
+    tpath = os.path.join(prof_dir, "prof_bench", "bench_kernel_trace.csv")
+    lpath = os.path.join(prof_dir, "prof_bench.log")
+    if not (os.path.exists(tpath) and os.path.exists(lpath)):
+        return []
+    line = [x for x in open(lpath) if x.startswith("{") and '"metric"' in x][-1]
+    b = json.loads(line)
+    ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                for r in csv.DictReader(open(tpath)) if "k_stream_persist" in r["Kernel_Name"])
+    runs = [ds[i:i + 3] for i in range(0, len(ds), 3)]
+    reps = max(2, min(5, b["steps"]))
+    assert len(runs) == AUTOTUNE_RUNS + b["warmup"] + b["steps"] + 1 + reps, len(runs)
+    assert all(len({k for _, _, k in r}) == 3 for r in runs)
+    timed = runs[AUTOTUNE_RUNS + b["warmup"]:AUTOTUNE_RUNS + b["warmup"] + b["steps"]]
+    spans = [(max(e for _, e, _ in r) - min(t for t, _, _ in r)) / 1e3 for r in timed]
+    mean = statistics.mean(spans)
+    ev = b["roofline"]["launch_us"]
+    return ["", "Persistent phase of the timed batch runs (three concurrent per-class launches, first start "
+                "to last end in the trace):", "",
+            "| run | span us |", "|---|---|"] + [f"| {k} | {x:.0f} |" for k, x in enumerate(spans)] + \
+           ["", f"Mean {mean:.0f} us; the bench line of the same run measured {ev:.0f} us with HIP events "
+                f"around the three launches ({(ev - mean) / mean * 100:+.1f}%).  Bench line: value "
+                f"{b['value']} GLUP/s, roofline frac {b['roofline']['frac']}, segments of at most "
+                f"{b['roofline']['rows_cap']} rows."]
 
 
 def main():

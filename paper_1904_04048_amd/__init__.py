@@ -26,7 +26,7 @@ __all__ = [
     "NOALLOC_MAX_BYTES", "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
     "wave2d_release", "wave2d_autotune", "wave2d_batch_create", "wave2d_batch_run", "wave2d_batch_stats_get", "wave2d_batch_autotune",
-    "wave2d_batch_destroy", "BATCH_GRAPH", "BATCH_ROUNDS", "wave2d_sine_series", "wave2d_server_create", "wave2d_server_submit",
+    "wave2d_batch_set_rows_cap", "wave2d_batch_destroy", "BATCH_GRAPH", "BATCH_ROUNDS", "wave2d_sine_series", "wave2d_server_create", "wave2d_server_submit",
     "wave2d_server_poll", "wave2d_server_release", "wave2d_server_stats_get", "wave2d_server_destroy",
 ]
 
@@ -238,6 +238,13 @@ def wave2d_batch_autotune(batch):
     cap = ctypes.c_int32(0)
     _lib.check(_lib.load().wave2d_batch_autotune(batch, s, ctypes.byref(cap)))
     return cap.value
+
+
+def wave2d_batch_set_rows_cap(batch, rows_cap):
+    """Re-plan the batch's persistent items for segments of at most rows_cap rows."""
+    import torch
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(_lib.load().wave2d_batch_set_rows_cap(batch, rows_cap, s))
 
 
 def wave2d_batch_destroy(batch):

@@ -91,6 +91,7 @@ _SIGS = {
     "wave2d_batch_run": (I, [P, P]),
     "wave2d_batch_stats_get": (I, [P, P]),
     "wave2d_batch_autotune": (I, [P, P, P]),
+    "wave2d_batch_set_rows_cap": (I, [P, ctypes.c_int32, P]),
     "wave2d_batch_destroy": (I, [P]),
     "wave2d_sine_series": (I, [I64, I64, I64, ctypes.c_int32, P, P, P, P]),
     "wave2d_server_create": (I, [SZ, U32, P]),

@@ -319,6 +319,33 @@ int enqueue(wave2d_batch* b, hipStream_t s, bool timing)
     return WAVE2D_OK;
 }
 
+// Re-plan the persistent tables for segments of at most `cap` rows and
+// upload them in place (the layout does not depend on `cap`).  Queue
+// membership follows the work model, which depends on the height, so every
+// per-class table is rewritten.
+int upload_plan(wave2d_batch* b, int cap, hipStream_t s)
+{
+    PersistPlan pl;
+    int r = plan_persist(b, cap, &pl);
+    if (r) return r;
+    char* base = (char*)b->tables;
+    W2D_HIP(hipStreamSynchronize(s));
+    W2D_HIP(hipMemcpy(base + b->p_insts, pl.recs.data(), pl.recs.size(), hipMemcpyHostToDevice));
+    W2D_HIP(hipMemcpy(base + b->p_tasks, pl.tasks.data(), pl.tasks.size() * sizeof(PersistTask),
+                      hipMemcpyHostToDevice));
+    for (int c = 0; c < kClasses; ++c) {
+        W2D_HIP(hipMemcpy(base + b->p_qoff[c], pl.qoff[c].data(), pl.qoff[c].size() * sizeof(int),
+                          hipMemcpyHostToDevice));
+        W2D_HIP(hipMemcpy(base + b->p_qn[c], pl.qn[c].data(), pl.qn[c].size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    b->st.items += pl.items - b->st.persistent_items;
+    b->st.item_rows += pl.item_rows - b->p_item_rows;
+    b->st.persistent_items = pl.items;
+    b->p_item_rows = pl.item_rows;
+    b->rows_cap = cap;
+    return WAVE2D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -689,34 +716,11 @@ int wave2d_batch_autotune(wave2d_batch* b, void* stream, int32_t* rows_cap)
             (void)hipEventDestroy(b);
         }
     } rel{e0, e1};
-    auto upload = [&](int cap) -> int {
-        PersistPlan pl;
-        int r = plan_persist(b, cap, &pl);
-        if (r) return r;
-        char* base = (char*)b->tables;
-        W2D_HIP(hipStreamSynchronize(s));
-        W2D_HIP(hipMemcpy(base + b->p_insts, pl.recs.data(), pl.recs.size(), hipMemcpyHostToDevice));
-        W2D_HIP(hipMemcpy(base + b->p_tasks, pl.tasks.data(), pl.tasks.size() * sizeof(PersistTask),
-                          hipMemcpyHostToDevice));
-        // Queue membership follows the work model, which depends on the
-        // height: every per-class table changes with it.
-        for (int c = 0; c < kClasses; ++c) {
-            W2D_HIP(hipMemcpy(base + b->p_qoff[c], pl.qoff[c].data(), pl.qoff[c].size() * sizeof(int),
-                              hipMemcpyHostToDevice));
-            W2D_HIP(hipMemcpy(base + b->p_qn[c], pl.qn[c].data(), pl.qn[c].size() * sizeof(int), hipMemcpyHostToDevice));
-        }
-        b->st.items += pl.items - b->st.persistent_items;
-        b->st.item_rows += pl.item_rows - b->p_item_rows;
-        b->st.persistent_items = pl.items;
-        b->p_item_rows = pl.item_rows;
-        b->rows_cap = cap;
-        return WAVE2D_OK;
-    };
     float best_ms = 1e30f;
     int best = b->rows_cap;
     int r;
     for (int cap : cand) {
-        if ((r = upload(cap))) return r;
+        if ((r = upload_plan(b, cap, s))) return r;
         if ((r = enqueue(b, s, true))) return r;  // warm-up
         float tot = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
@@ -733,10 +737,18 @@ int wave2d_batch_autotune(wave2d_batch* b, void* stream, int32_t* rows_cap)
             best = cap;
         }
     }
-    if ((r = upload(best))) return r;
+    if ((r = upload_plan(b, best, s))) return r;
     b->ran = true;
     if (rows_cap) *rows_cap = best;
     return WAVE2D_OK;
+}
+
+int wave2d_batch_set_rows_cap(wave2d_batch* b, int32_t rows_cap, void* stream)
+{
+    if (!b) return fail(WAVE2D_EINVAL, "batch is NULL");
+    if (rows_cap < 8 || rows_cap > 4096) return fail(WAVE2D_EINVAL, "rows_cap %d outside 8..4096", (int)rows_cap);
+    if (!b->persist) return WAVE2D_OK;
+    return upload_plan(b, rows_cap, (hipStream_t)stream);
 }
 
 int wave2d_batch_destroy(wave2d_batch* b)

@@ -247,3 +247,21 @@ def test_persistent_batch_autotune_keeps_results():
                 assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (rep, k)
     finally:
         w.wave2d_batch_destroy(b)
+    # The tuned height applied to another batch of the same instances, and
+    # other heights down to the smallest accepted, keep the results.
+    b = w.wave2d_batch_create(insts, w.BATCH_GRAPH)
+    try:
+        with pytest.raises(w.Wave2dError):
+            w.wave2d_batch_set_rows_cap(b, 7)
+        with pytest.raises(w.Wave2dError):
+            w.wave2d_batch_set_rows_cap(b, 4097)
+        for c in (cap, 8, 1000):
+            w.wave2d_batch_set_rows_cap(b, c)
+            _clear(insts)
+            w.wave2d_batch_run(b)
+            torch.cuda.synchronize()
+            assert w.wave2d_batch_stats_get(b)["stalled_waits"] == 0
+            for k, (t, (u, lo, d)) in enumerate(zip(insts, refs)):
+                assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (c, k)
+    finally:
+        w.wave2d_batch_destroy(b)
