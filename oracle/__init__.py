@@ -72,7 +72,9 @@ def lib():
         L.orc_run.restype = I
         L.orc_norms.argtypes = [Lg, P, P, P]
         L.orc_norms.restype = None
-        L.orc_set_scheme.argtypes = [I, I, P, P]
+        L.orc_set_scheme.argtypes = [I, I, I, P, P]
+        L.orc_class_brackets.argtypes = [I, D, P, P, P]
+        L.orc_class_brackets.restype = I
         L.orc_set_scheme.restype = I
         L.orc_set_threads.argtypes = [I]
         L.orc_set_threads.restype = None
@@ -113,31 +115,64 @@ def brackets(scheme: int, lam: float):
 
 CUSTOM_DEG = 12
 
+# Node classes of a symmetric stencil up to three lines from the centre, in
+# the C oracle's order: class (q1, q2) holds (+-q1, +-q2) and (+-q2, +-q1).
+CLASSES = ((1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (3, 3))
+
+
+def class_nodes(q1: int, q2: int):
+    """The nodes of class (q1, q2): four on an axis or diagonal, else eight."""
+    return sorted({(sx * a, sy * b) for (a, b) in ((q1, q2), (q2, q1)) for sx in (1, -1) for sy in (1, -1)})
+
 
 def register_scheme(scheme_id: int, weights) -> None:
     """Make scheme_id (1000..1015) run the scheme with these node weights:
     {node: (A, B / tau)} as polynomials in lambda ({power: coefficient}),
-    e.g. from ``derive.node_weights_for``.  One node of each class (axis 1,
-    diagonal, axis 2) gives that class's weights; a class without nodes has
-    none.  First step eq. A1, two-step update eq. A2."""
-    a = np.zeros((3, CUSTOM_DEG + 1))
-    b = np.zeros((3, CUSTOM_DEG + 1))
-    reps = {(1, 0): 0, (1, 1): 1, (2, 0): 2}
+    e.g. from ``derive.node_weights_for``.  Every node of a class must carry
+    the same weights, and a class with weight must have all its nodes;
+    nodes more than three lines from the centre must carry none.  First
+    step eq. A1, two-step update eq. A2."""
+    a = np.zeros((len(CLASSES), CUSTOM_DEG + 1))
+    b = np.zeros((len(CLASSES), CUSTOM_DEG + 1))
+    index = {c: k for k, c in enumerate(CLASSES)}
+    per_class = {}
     for q, (A, B) in weights.items():
         key = tuple(sorted((abs(q[0]), abs(q[1])), reverse=True))
         if key == (0, 0):
-            continue  # the centre weight is one minus the others (eq. A1, A2 as rotation sums)
-        if key not in reps:
-            if any(A.values()) or any(B.values()):
-                raise ValueError(f"node {q} carries weight outside the 13-point classes")
+            continue  # the centre weight is one minus the others (eq. A1, A2 as class sums)
+        has = any(A.values()) or any(B.values())
+        if key not in index:
+            if has:
+                raise ValueError(f"node {q} carries weight more than three lines from the centre")
             continue
-        c = reps[key]
-        for p_, v in A.items():
+        per_class.setdefault(key, []).append((tuple(q), dict(A), dict(B), has))
+    for key, nodes in per_class.items():
+        if not any(n[3] for n in nodes):
+            continue
+        if sorted(n[0] for n in nodes) != class_nodes(*key):
+            raise ValueError(f"class {key} carries weight but the stencil lacks some of its nodes")
+        ref = nodes[0]
+        for n in nodes[1:]:
+            if n[1] != ref[1] or n[2] != ref[2]:
+                raise ValueError(f"node {n[0]} has other weights than {ref[0]} of the same class")
+        c = index[key]
+        for p_, v in ref[1].items():
             a[c, p_] = float(v)
-        for p_, v in B.items():
+        for p_, v in ref[2].items():
             b[c, p_] = float(v)
-    if lib().orc_set_scheme(int(scheme_id), CUSTOM_DEG, _ptr(a), _ptr(b)):
+    if lib().orc_set_scheme(int(scheme_id), len(CLASSES), CUSTOM_DEG, _ptr(a), _ptr(b)):
         raise ValueError(f"bad custom scheme id {scheme_id}")
+
+
+def class_brackets(scheme: int, lam: float):
+    """(a[9], b[9], has_b): brackets of every class of CLASSES, normalised as
+    in ``brackets`` (zero for the classes a scheme does not use)."""
+    a = np.zeros(len(CLASSES))
+    b = np.zeros(len(CLASSES))
+    hb = ctypes.c_int(0)
+    if lib().orc_class_brackets(int(scheme), float(lam), _ptr(a), _ptr(b), ctypes.byref(hb)):
+        raise ValueError(f"unknown scheme {scheme}")
+    return a, b, bool(hb.value)
 
 
 def lambda_max(scheme: int) -> float:
