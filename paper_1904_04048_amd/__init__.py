@@ -21,7 +21,7 @@ from ._lib import (ALLOW_UNSTABLE, BATCH_GRAPH, BATCH_ROUNDS, C9, F32C, F64, FIR
 
 __all__ = [
     "P5", "P9", "P13", "C9", "F64", "F32C", "FIRST_CONVENTIONAL", "ALLOW_UNSTABLE", "KERNEL_SIMPLE", "PERIODIC",
-    "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_work_bytes", "wave2d_first_step",
+    "Wave2dError", "wave2d_lambda_max", "wave2d_weights", "wave2d_class_weights", "CLASSES", "wave2d_work_bytes", "wave2d_first_step",
     "wave2d_step", "wave2d_run", "wave2d_f32c_init", "wave2d_f32c_step", "wave2d_f32c_step_noalloc",
     "NOALLOC_MAX_BYTES", "wave2d_f32c_export",
     "wave2d_f32c_run", "wave2d_norms", "wave2d_f32c_norms", "wave2d_set_tuning", "wave2d_get_tuning",
@@ -90,6 +90,16 @@ def wave2d_weights(scheme: int, lam: float, flags: int = 0):
     """(w2, wa, wb): two-step weights and first-step A / (B/tau) node weights."""
     w2, wa, wb = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
     _lib.check(_lib.load().wave2d_weights(scheme, flags, lam, w2, wa, wb))
+    return list(w2), list(wa), list(wb)
+
+
+CLASSES = ((1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (3, 3))
+
+
+def wave2d_class_weights(scheme: int, lam: float, flags: int = 0, nclass: int = 9):
+    """(w2, wa, wb) for the first nclass node classes of CLASSES."""
+    w2, wa, wb = (ctypes.c_double * nclass)(), (ctypes.c_double * nclass)(), (ctypes.c_double * nclass)()
+    _lib.check(_lib.load().wave2d_class_weights(scheme, flags, lam, nclass, w2, wa, wb))
     return list(w2), list(wa), list(wb)
 
 

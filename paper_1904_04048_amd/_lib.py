@@ -70,6 +70,7 @@ _SIGS = {
     "wave2d_lambda_max": (D, [I]),
     "wave2d_scheme_create": (I, [ctypes.c_int32, P, P, P]),
     "wave2d_weights": (I, [I, U32, D, P, P, P]),
+    "wave2d_class_weights": (I, [I, U32, D, ctypes.c_int32, P, P, P]),
     "wave2d_status_str": (ctypes.c_char_p, [I]),
     "wave2d_last_error": (ctypes.c_char_p, []),
     "wave2d_work_bytes": (SZ, [I, I64, I64, I64]),

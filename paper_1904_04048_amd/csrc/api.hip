@@ -70,8 +70,9 @@ int scheme_index(int scheme)
     case WAVE2D_P13: return 2;
     case WAVE2D_C9: return 3;
     default: {
+        // KINDW schemes run one level per launch: no launch shape to tune.
         CustomScheme cs;
-        if (!custom_scheme(scheme, &cs)) return -1;
+        if (!custom_scheme(scheme, &cs) || cs.kind == KINDW) return -1;
         return cs.kind == KIND5 ? 0 : cs.kind == KIND9 ? 1 : 2;
     }
     }
@@ -86,8 +87,10 @@ int tuning_scheme(int scheme)
     return si == 0 ? WAVE2D_P5 : si == 1 ? WAVE2D_P9 : WAVE2D_P13;
 }
 
-// Node weights of the A and B operators for one neighbour of each class
-// (axis at distance 1, diagonal, axis at distance 2); B divided by tau.
+// Node weights of the A and B operators for one node of each class (the
+// order of Params: axis at distance 1, diagonal, axis at distance 2, then
+// the classes out to three lines, which only built schemes use); B divided
+// by tau.
 //   five-point:  A: lambda^2/2 (Sec. 6.1, eq. A6); B: lambda^2/6 (eq. B6)
 //   nine-point:  A: lambda^2/2 - lambda^4/6, lambda^4/12 (eq. A11)
 //                B: lambda^2/6 - lambda^4/30, lambda^4/60 (eq. B11)
@@ -96,10 +99,11 @@ int tuning_scheme(int scheme)
 //                B: lambda^2 (10 - 3 lambda^2)/45, lambda^4/60, lambda^2 (3 lambda^2 - 5)/360
 //   isotropic:   eq. comp9.1b / comp9.2b: A: lambda^2/3, lambda^2/12; no B stencil.
 // The two-step weights are twice the A weights (Sec. 3, eq. A2).
-bool node_weights(int scheme, double lam, double wa[3], double wb[3], bool* has_b)
+bool node_weights(int scheme, double lam, double wa[kWideClasses], double wb[kWideClasses], bool* has_b)
 {
     const double l2 = lam * lam, l4 = l2 * l2;
     *has_b = true;
+    for (int c = 0; c < kWideClasses; ++c) wa[c] = wb[c] = 0.0;
     switch (scheme) {
     case WAVE2D_P5:
         wa[0] = l2 / 2.0; wa[1] = 0.0; wa[2] = 0.0;
@@ -122,7 +126,7 @@ bool node_weights(int scheme, double lam, double wa[3], double wb[3], bool* has_
         // Built schemes: the polynomials of the Sec. 4-5 construction.
         CustomScheme cs;
         if (!custom_scheme(scheme, &cs)) return false;
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < kWideClasses; ++c) {
             double sa = 0.0, sb = 0.0;
             for (int k = CustomScheme::kDeg; k >= 0; --k) {
                 sa = sa * lam + cs.a[c][k];
@@ -178,7 +182,7 @@ int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c,
     if (p->kind < 0) return fail(WAVE2D_EINVAL, "unknown scheme %d", scheme);
     p->g = Grid{(int)nx, (int)ny, (int)ld, (flags & WAVE2D_PERIODIC) ? 1 : 0};
     if (p->g.periodic) {
-        const int rr = (p->kind == KIND13) ? 2 : 1;
+        const int rr = radius_of_kind(p->kind);
         if (nx < 2 * rr + 1 || ny < 2 * rr + 1)
             return fail(WAVE2D_EINVAL, "periodic grids need at least %d x %d nodes for scheme %d", 2 * rr + 1,
                         2 * rr + 1, scheme);
@@ -216,6 +220,38 @@ StepW32 step_w32(const Params& p)
     const double wx = 2.0 * p.wa[0] + 4.0 * p.wa[1] + 8.0 * p.wa[2];
     w.wx = (float)wx;
     w.wxl = (float)(wx - (double)w.wx);
+    return w;
+}
+
+int radius_of_kind(int kind) { return kind == KINDW ? 3 : kind == KIND13 ? 2 : 1; }
+
+WideW64 wide_w64(const Params& p)
+{
+    WideW64 w;
+    for (int c = 0; c < kWideClasses; ++c) w.w[c] = 2.0 * p.wa[c];
+    return w;
+}
+
+WideW32 wide_w32(const Params& p)
+{
+    WideW32 w;
+    for (int c = 0; c < kWideClasses; ++c) {
+        const double x = 2.0 * p.wa[c];
+        w.w[c] = (float)x;
+        w.wl[c] = (float)(x - (double)w.w[c]);
+    }
+    return w;
+}
+
+WideFirstW wide_first_w(const Params& p, uint32_t flags, double tau)
+{
+    WideFirstW w;
+    for (int c = 0; c < kWideClasses; ++c) {
+        w.a[c] = p.wa[c];
+        w.b[c] = p.wb[c];
+    }
+    w.tau = tau;
+    w.poisson = (p.has_b && !(flags & WAVE2D_FIRST_CONVENTIONAL)) ? 1 : 0;
     return w;
 }
 
@@ -565,8 +601,20 @@ int run_steps_f64(const Params& p, uint32_t flags, int64_t steps, double* up, do
                   size_t work_bytes, hipStream_t s)
 {
     if (steps == 0) return WAVE2D_OK;
-    const StepW64 w = step_w64(p);
     const Grid& g = p.g;
+    if (p.kind == KINDW) {
+        // One level per launch, in place: level k+1 overwrites level k-1.
+        const WideW64 ww = wide_w64(p);
+        double* a = up;
+        double* b = uc;
+        for (int64_t k = 0; k < steps; ++k) {
+            W2D_HIP(wide_step_f64(g, ww, a, b, a, s));
+            std::swap(a, b);
+        }
+        if (steps % 2) W2D_HIP(swap_f64(g, up, uc, s));
+        return WAVE2D_OK;
+    }
+    const StepW64 w = step_w64(p);
     const wave2d_tuning tn = tuning_for(WAVE2D_F64, p.scheme, g.nx, g.ny);
     const bool simple = (flags & WAVE2D_KERNEL_SIMPLE) || !stream_ok(g, sizeof(double));
     if (simple || tn.depth == 1 || steps == 1) {
@@ -615,6 +663,18 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
     float* wu = (float*)base;
     float* wl = (float*)(base + stride);
     float* wd = (float*)(base + 2 * stride);
+    if (p.kind == KINDW) {
+        const WideW32 ww = wide_w32(p);
+        float *iu = u, *il = lo, *id = d, *ou = wu, *ol = wl, *od = wd;
+        for (int64_t k = 0; k < steps; ++k) {
+            W2D_HIP(wide_step_f32c(g, ww, iu, il, id, ou, ol, od, s));
+            std::swap(iu, ou);
+            std::swap(il, ol);
+            std::swap(id, od);
+        }
+        if (iu != u) W2D_HIP(copy_f32x3(g, iu, il, id, u, lo, d, s));
+        return WAVE2D_OK;
+    }
     const bool simple = (flags & WAVE2D_KERNEL_SIMPLE) || !stream_ok(g, sizeof(float));
     const wave2d_tuning tn = tuning_for(WAVE2D_F32C, p.scheme, g.nx, g.ny);
     bool needs_copy = false;
@@ -630,6 +690,15 @@ int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, flo
         std::swap(id, od);
     }
     if (iu != u) W2D_HIP(copy_f32x3(g, iu, il, id, u, lo, d, s));
+    return WAVE2D_OK;
+}
+
+// FP64 first step (eq. A1) with the kernels of the scheme's class.
+int first_step_any(const Params& p, uint32_t flags, double tau, const double* u0, const double* v0, double* u1,
+                   hipStream_t s)
+{
+    if (p.kind == KINDW) W2D_HIP(wide_first_step(p.g, wide_first_w(p, flags, tau), u0, v0, u1, s));
+    else W2D_HIP(simple_first_step(p.g, p.kind, first_w(p, flags, tau), u0, v0, u1, s));
     return WAVE2D_OK;
 }
 
@@ -696,19 +765,29 @@ int wave2d_scheme_create(int32_t m, const int32_t* nodes, const int32_t* exps, i
     return custom_scheme_create(m, nodes, exps, scheme);
 }
 
-int wave2d_weights(int scheme, uint32_t flags, double lambda, double w2[3], double wa[3], double wb[3])
+int wave2d_class_weights(int scheme, uint32_t flags, double lambda, int32_t nclass, double* w2, double* wa,
+                         double* wb)
 {
-    double a[3], b[3];
+    double a[kWideClasses], b[kWideClasses];
     bool hb;
     if (!(std::isfinite(lambda) && lambda >= 0.0)) return fail(WAVE2D_EINVAL, "lambda must be finite and >= 0");
+    if (nclass < 1 || nclass > kWideClasses) return fail(WAVE2D_EINVAL, "nclass must be in [1, %d]", kWideClasses);
     if (!node_weights(scheme, lambda, a, b, &hb)) return fail(WAVE2D_EINVAL, "unknown scheme %d", scheme);
+    for (int q = nclass; q < kWideClasses; ++q)
+        if (a[q] != 0.0 || b[q] != 0.0)
+            return fail(WAVE2D_EINVAL, "scheme %d has weight in class %d, beyond the %d requested", scheme, q, nclass);
     const bool poisson = hb && !(flags & WAVE2D_FIRST_CONVENTIONAL);
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < nclass; ++q) {
         if (w2) w2[q] = 2.0 * a[q];
         if (wa) wa[q] = a[q];
         if (wb) wb[q] = poisson ? b[q] : 0.0;
     }
     return WAVE2D_OK;
+}
+
+int wave2d_weights(int scheme, uint32_t flags, double lambda, double w2[3], double wa[3], double wb[3])
+{
+    return wave2d_class_weights(scheme, flags, lambda, 3, w2, wa, wb);
 }
 
 const char* wave2d_status_str(int status)
@@ -740,8 +819,7 @@ int wave2d_first_step(int64_t nx, int64_t ny, int64_t ld, double h, double tau, 
     int r = validate(nx, ny, ld, h, tau, c, scheme, flags, &p);
     if (r) return r;
     if ((r = check_ptrs(p.g, {{u0, 8}, {v0, 8}, {u1, 8}}))) return r;
-    W2D_HIP(simple_first_step(p.g, p.kind, first_w(p, flags, tau), u0, v0, u1, (hipStream_t)stream));
-    return WAVE2D_OK;
+    return first_step_any(p, flags, tau, u0, v0, u1, (hipStream_t)stream);
 }
 
 int wave2d_step(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c, int scheme, uint32_t flags,
@@ -766,7 +844,7 @@ int wave2d_run(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double 
     if ((r = check_ptrs(p.g, {{u0, 8}, {v0, 8}, {u_prev_out, 8}, {u_out, 8}}))) return r;
     hipStream_t s = (hipStream_t)stream;
     W2D_HIP(copy_interior_f64(p.g, u0, u_prev_out, s));
-    W2D_HIP(simple_first_step(p.g, p.kind, first_w(p, flags, tau), u0, v0, u_out, s));
+    if ((r = first_step_any(p, flags, tau, u0, v0, u_out, s))) return r;
     return run_steps_f64(p, flags, steps - 1, u_prev_out, u_out, work, work_bytes, s);
 }
 
@@ -814,7 +892,8 @@ int wave2d_f32c_run(int64_t nx, int64_t ny, int64_t ld, double h, double tau, do
     if (steps < 1) return fail(WAVE2D_EINVAL, "steps must be >= 1");
     if ((r = check_ptrs(p.g, {{u0, 8}, {v0, 8}, {u, 4}, {lo, 4}, {d, 4}}))) return r;
     hipStream_t s = (hipStream_t)stream;
-    W2D_HIP(simple_first_step_f32c(p.g, p.kind, first_w(p, flags, tau), u0, v0, u, lo, d, s));
+    if (p.kind == KINDW) W2D_HIP(wide_first_step_f32c(p.g, wide_first_w(p, flags, tau), u0, v0, u, lo, d, s));
+    else W2D_HIP(simple_first_step_f32c(p.g, p.kind, first_w(p, flags, tau), u0, v0, u, lo, d, s));
     return run_steps_f32c(p, flags, steps - 1, u, lo, d, work, work_bytes, s);
 }
 
@@ -859,6 +938,7 @@ int wave2d_f32c_norms(int64_t nx, int64_t ny, int64_t ld, const float* u, const 
 int wave2d_set_tuning(int precision, int scheme, const wave2d_tuning* t)
 {
     if (precision != WAVE2D_F64 && precision != WAVE2D_F32C) return fail(WAVE2D_EINVAL, "unknown precision");
+    if (kind_of(scheme) == KINDW) return fail(WAVE2D_EINVAL, "scheme %d runs one level per launch: no tuning", scheme);
     const int si = scheme_index(scheme);
     if (si < 0) return fail(WAVE2D_EINVAL, "unknown scheme %d", scheme);
     if (t) {
@@ -879,6 +959,7 @@ int wave2d_set_tuning(int precision, int scheme, const wave2d_tuning* t)
 int wave2d_get_tuning(int precision, int scheme, int64_t nx, int64_t ny, wave2d_tuning* t)
 {
     if (precision != WAVE2D_F64 && precision != WAVE2D_F32C) return fail(WAVE2D_EINVAL, "unknown precision");
+    if (kind_of(scheme) == KINDW) return fail(WAVE2D_EINVAL, "scheme %d runs one level per launch: no tuning", scheme);
     if (scheme_index(scheme) < 0) return fail(WAVE2D_EINVAL, "unknown scheme %d", scheme);
     if (!t) return fail(WAVE2D_EINVAL, "t is NULL");
     *t = tuning_for(precision, scheme, nx, ny);

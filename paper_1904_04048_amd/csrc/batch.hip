@@ -380,6 +380,13 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
             delete b;
             return fail(WAVE2D_EINVAL, "instance %lld: steps must be >= 1", (long long)i);
         }
+        if (rec.p.kind == KINDW) {
+            delete b;
+            return fail(WAVE2D_EINVAL,
+                        "instance %lld: scheme %d reaches three lines out; batches take the 5-, 9- and 13-point "
+                        "classes (run it with wave2d_f32c_run)",
+                        (long long)i, in.scheme);
+        }
         if (!stream_ok(rec.p.g, sizeof(float))) {
             delete b;
             return fail(WAVE2D_EINVAL, "instance %lld: periodic batch instances need an even nx and ld*ny*4 < 2^31",
@@ -773,6 +780,7 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
     const double lam = 0.5 * wave2d_lambda_max(scheme);
     int r = validate(nx, ny, nx, 1.0, lam, 1.0, scheme, 0, &p);
     if (r) return r;
+    if (p.kind == KINDW) return fail(WAVE2D_EINVAL, "scheme %d runs one level per launch: no launch shape to tune", scheme);
     hipStream_t s = (hipStream_t)stream;
     const size_t n = (size_t)nx * ny;
     const size_t elt = precision == WAVE2D_F64 ? 8 : 4;

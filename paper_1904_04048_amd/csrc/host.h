@@ -11,6 +11,7 @@
 
 #include "w2d.h"
 #include "wave2d.h"
+#include "wide.h"
 
 namespace w2d_host {
 
@@ -20,23 +21,26 @@ using w2d::Grid;
 using w2d::StepW32;
 using w2d::StepW64;
 
+// Node weights per class (q1, q2) in the order (1,0), (1,1), (2,0), (2,1),
+// (2,2), (3,0), (3,1), (3,2), (3,3); the schemes of Sec. 6 use the first
+// three.
 struct Params {
     Grid g;
     int scheme;
     int kind;
     double lam;
-    double wa[3], wb[3];
+    double wa[w2d::kWideClasses], wb[w2d::kWideClasses];
     bool has_b;
 };
 
-// A scheme built by wave2d_scheme_create: per class (axis 1, diagonal,
-// axis 2) the node weights of A and of B / tau as polynomials in lambda
+// A scheme built by wave2d_scheme_create: per node class (the order of
+// Params) the node weights of A and of B / tau as polynomials in lambda
 // (coefficient k of lambda^k), the stencil class the kernels run it as,
 // and its stability limit.
 struct CustomScheme {
     static constexpr int kDeg = 12;
-    double a[3][kDeg + 1];
-    double b[3][kDeg + 1];
+    double a[w2d::kWideClasses][kDeg + 1];
+    double b[w2d::kWideClasses][kDeg + 1];
     int kind;
     double lambda_max;
 };
@@ -52,6 +56,11 @@ int validate(int64_t nx, int64_t ny, int64_t ld, double h, double tau, double c,
 StepW64 step_w64(const Params& p);
 StepW32 step_w32(const Params& p);
 FirstW first_w(const Params& p, uint32_t flags, double tau);
+w2d::WideW64 wide_w64(const Params& p);
+w2d::WideW32 wide_w32(const Params& p);
+w2d::WideFirstW wide_first_w(const Params& p, uint32_t flags, double tau);
+// Stencil radius of a kind (KIND5/9: 1, KIND13: 2, KINDW: 3).
+int radius_of_kind(int kind);
 bool overlap(const void* a, size_t na, const void* b, size_t nb);
 size_t grid_bytes(const Grid& g, size_t elt);
 int check_ptrs(const Grid& g, std::initializer_list<std::pair<const void*, size_t>> arrs);

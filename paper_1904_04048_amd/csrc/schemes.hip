@@ -17,14 +17,19 @@
 // that Lap^j leaves of a monomial of degree 2j (0 unless both exponents are
 // even).
 //
-// The weights must be those of a scheme the stencil kernels run: symmetric
-// under the eight symmetries of the square and zero outside the centre and
-// the classes (1,0), (1,1), (2,0).  The stability limit is found
+// The weights must be those of a scheme the kernels run: symmetric under
+// the eight symmetries of the square and zero more than three lines from
+// the centre, so that they are constant on the node classes (q1, q2),
+// q1 >= q2 >= 0, q1 <= 3 (the nodes (+-q1, +-q2) and (+-q2, +-q1)).
+// Schemes with weight only on (1,0), (1,1), (2,0) run as the 5-, 9- or
+// 13-point class; the others as KINDW.  The stability limit is found
 // numerically from the two-step symbol (von Neumann): with
-// S(theta) = sum_c 2 A_c(lambda) sigma_c(theta), sigma_10 = 2 cos t1 +
-// 2 cos t2 - 4, sigma_11 = 4 cos t1 cos t2 - 4, sigma_20 = 2 cos 2t1 +
-// 2 cos 2t2 - 4, the update u^{k+1} - 2u^k + u^{k-1} = S u^k keeps every
-// mode bounded iff -4 <= S <= 0 for all theta.
+// S(theta) = sum_c 2 A_c(lambda) sigma_c(theta) and sigma_c the sum over
+// the class's nodes of cos(q . theta) - 1 (sigma_10 = 2 cos t1 + 2 cos t2 -
+// 4, sigma_11 = 4 cos t1 cos t2 - 4, sigma_20 = 2 cos 2t1 + 2 cos 2t2 - 4,
+// and for an eight-node class 4 cos q1t1 cos q2t2 + 4 cos q2t1 cos q1t2 -
+// 8), the update u^{k+1} - 2u^k + u^{k-1} = S u^k keeps every mode bounded
+// iff -4 <= S <= 0 for all theta.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -40,6 +45,10 @@ namespace {
 using w2d::KIND13;
 using w2d::KIND5;
 using w2d::KIND9;
+using w2d::KINDW;
+using w2d::kWideClasses;
+
+constexpr int kQ[kWideClasses][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}, {3, 0}, {3, 1}, {3, 2}, {3, 3}};
 
 constexpr int kMaxNodes = 64;
 constexpr int kMaxExp = 12;
@@ -119,12 +128,20 @@ double poly_eval(const double* p, int deg, double x)
 // a grid, then a local refinement of the grid's extreme points.
 void symbol_range(const CustomScheme& s, double lam, double* smin, double* smax)
 {
-    double w[3];
-    for (int c = 0; c < 3; ++c) w[c] = 2.0 * poly_eval(s.a[c], CustomScheme::kDeg, lam);
+    double w[kWideClasses];
+    for (int c = 0; c < kWideClasses; ++c) w[c] = 2.0 * poly_eval(s.a[c], CustomScheme::kDeg, lam);
     auto S = [&](double t1, double t2) {
-        const double c1 = std::cos(t1), c2 = std::cos(t2);
-        return w[0] * (2.0 * c1 + 2.0 * c2 - 4.0) + w[1] * (4.0 * c1 * c2 - 4.0) +
-               w[2] * (2.0 * std::cos(2.0 * t1) + 2.0 * std::cos(2.0 * t2) - 4.0);
+        double v = 0.0;
+        for (int c = 0; c < kWideClasses; ++c) {
+            if (w[c] == 0.0) continue;
+            const int q1 = kQ[c][0], q2 = kQ[c][1];
+            double sig;
+            if (q2 == 0) sig = 2.0 * std::cos(q1 * t1) + 2.0 * std::cos(q1 * t2) - 4.0;
+            else if (q1 == q2) sig = 4.0 * std::cos(q1 * t1) * std::cos(q1 * t2) - 4.0;
+            else sig = 4.0 * std::cos(q1 * t1) * std::cos(q2 * t2) + 4.0 * std::cos(q2 * t1) * std::cos(q1 * t2) - 8.0;
+            v += w[c] * sig;
+        }
+        return v;
     };
     constexpr int N = 128;
     const double dt = M_PI / N;
@@ -190,16 +207,19 @@ double stability_limit(const CustomScheme& s)
     return ok;
 }
 
+// Index of the class of node (q1, q2) in kQ; -1 for the centre,
+// kWideClasses for a node more than three lines out.
 int class_of(int q1, int q2)
 {
     const int a = std::abs(q1), b = std::abs(q2);
     const int hi = std::max(a, b), lo = std::min(a, b);
-    if (hi == 0) return -1;  // centre
-    if (hi == 1 && lo == 0) return 0;
-    if (hi == 1 && lo == 1) return 1;
-    if (hi == 2 && lo == 0) return 2;
-    return 3;  // not a class the kernels implement
+    if (hi == 0) return -1;
+    for (int c = 0; c < kWideClasses; ++c)
+        if (kQ[c][0] == hi && kQ[c][1] == lo) return c;
+    return kWideClasses;
 }
+
+int class_size(int c) { return (kQ[c][1] == 0 || kQ[c][1] == kQ[c][0]) ? 4 : 8; }
 
 }  // namespace
 
@@ -254,7 +274,7 @@ int custom_scheme_create(int m, const int32_t* nodes, const int32_t* exps, int* 
     // Classes: every node of a class carries the same polynomials; nodes
     // outside the kernels' classes must carry zero weight.
     CustomScheme cs{};
-    bool seen[3] = {false, false, false};
+    bool seen[kWideClasses] = {};
     double scale = 0.0;
     for (double v : Aw) scale = std::max(scale, std::fabs(v));
     for (double v : Bw) scale = std::max(scale, std::fabs(v));
@@ -280,12 +300,12 @@ int custom_scheme_create(int m, const int32_t* nodes, const int32_t* exps, int* 
         return true;
     };
     for (int r = 0; r < m; ++r)
-        if (class_of(nodes[2 * r], nodes[2 * r + 1]) == 3 && !is_zero(r))
-            return fail(WAVE2D_EINVAL, "node (%d, %d) has nonzero weight outside the 13-point classes",
+        if (class_of(nodes[2 * r], nodes[2 * r + 1]) == kWideClasses && !is_zero(r))
+            return fail(WAVE2D_EINVAL, "node (%d, %d) has nonzero weight more than three lines from the centre",
                         nodes[2 * r], nodes[2 * r + 1]);
     // Each class: every node equals the class's first node; a class with
-    // weight needs all four of its nodes.
-    for (int c = 0; c < 3; ++c) {
+    // weight needs all of its four or eight nodes.
+    for (int c = 0; c < kWideClasses; ++c) {
         int ref = -1, count = 0;
         for (int r = 0; r < m; ++r) {
             if (class_of(nodes[2 * r], nodes[2 * r + 1]) != c) continue;
@@ -304,22 +324,25 @@ int custom_scheme_create(int m, const int32_t* nodes, const int32_t* exps, int* 
                                 nodes[2 * r], nodes[2 * r + 1]);
         }
         if (ref < 0 || is_zero(ref)) continue;
-        if (count != 4)
-            return fail(WAVE2D_EINVAL, "class %d carries weight but the stencil has %d of its 4 nodes", c, count);
+        if (count != class_size(c))
+            return fail(WAVE2D_EINVAL, "class (%d, %d) carries weight but the stencil has %d of its %d nodes", kQ[c][0],
+                        kQ[c][1], count, class_size(c));
         seen[c] = true;
         std::copy(&Aw[(size_t)ref * (CustomScheme::kDeg + 1)], &Aw[(size_t)ref * (CustomScheme::kDeg + 1)] + CustomScheme::kDeg + 1, cs.a[c]);
         std::copy(&Bw[(size_t)ref * (CustomScheme::kDeg + 1)], &Bw[(size_t)ref * (CustomScheme::kDeg + 1)] + CustomScheme::kDeg + 1, cs.b[c]);
     }
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < kWideClasses; ++c)
         for (int k = 0; k <= CustomScheme::kDeg; ++k) {
             if (std::fabs(cs.a[c][k]) <= tol) cs.a[c][k] = 0.0;
             if (std::fabs(cs.b[c][k]) <= tol) cs.b[c][k] = 0.0;
         }
     bool any = false;
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < kWideClasses; ++c)
         for (int k = 0; k <= CustomScheme::kDeg; ++k) any = any || cs.a[c][k] != 0.0;
     if (!any) return fail(WAVE2D_EINVAL, "the scheme has no stencil weights");
-    cs.kind = seen[2] ? KIND13 : (seen[1] ? KIND9 : KIND5);
+    bool wide = false;
+    for (int c = 3; c < kWideClasses; ++c) wide = wide || seen[c];
+    cs.kind = wide ? KINDW : seen[2] ? KIND13 : (seen[1] ? KIND9 : KIND5);
     cs.lambda_max = stability_limit(cs);
     if (!(cs.lambda_max > 0.0)) return fail(WAVE2D_EINVAL, "the scheme is unstable for every Courant number");
     std::lock_guard<std::mutex> lk(g_mu);

@@ -485,6 +485,9 @@ int wave2d_server_submit(wave2d_server* sv, const wave2d_request* rq, uint64_t* 
     int rc = validate(rq->nx, rq->ny, rq->nx, rq->h, rq->tau, rq->c, rq->scheme,
                       rq->flags & ~(uint32_t)WAVE2D_KERNEL_SIMPLE, &r->p);
     if (!rc && rq->steps < 1) rc = fail(WAVE2D_EINVAL, "steps must be >= 1");
+    if (!rc && r->p.kind == KINDW)
+        rc = fail(WAVE2D_EINVAL, "scheme %d reaches three lines out; the server takes the 5-, 9- and 13-point classes",
+                  rq->scheme);
     if (!rc && !stream_ok(r->p.g, sizeof(float)))
         rc = fail(WAVE2D_EINVAL, "periodic requests need an even nx and nx*ny*4 < 2^31");
     if (!rc && (rq->nmodes < 0 || rq->nmodes > kMaxModes || (rq->nmodes > 0 && !rq->modes)))

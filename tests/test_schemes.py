@@ -137,9 +137,12 @@ def test_library_limit_against_brute_force_stepping(cross_oracle):
 @pytest.mark.parametrize("nodes,exps,msg", [
     (C0 + AX1, [(0, 0), (1, 0), (0, 1), (2, 0), (3, 0)], "not unisolvent"),
     (C0 + AX1[:3] + [(1, 1)], [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1)], "symmetric"),
+    (C0 + AX1 + AX2 + [(4, 0), (-4, 0), (0, 4), (0, -4)],
+     [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (3, 0), (0, 3), (4, 0), (0, 4), (5, 0), (0, 5), (6, 0), (0, 6)],
+     "more than three lines"),
     (C0 + AX1 + [(2, 1), (-2, 1), (-2, -1), (2, -1), (1, 2), (-1, 2), (-1, -2), (1, -2)],
      [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (0, 3), (0, 4), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (3, 0)],
-     "outside the 13-point classes"),
+     "symmetric"),
     (AX1 + AX2 + [(1, 1)], [(1, 0), (0, 1), (2, 0), (0, 2), (3, 0), (0, 3), (4, 0), (0, 4), (2, 2)], "constants"),
     (C0 + C0, [(0, 0), (1, 0)], "appears twice"),
     (C0 + [(9, 0)], [(0, 0), (1, 0)], "more than 8"),
@@ -180,3 +183,59 @@ def test_other_sets_with_the_same_even_part_give_the_paper_schemes(nodes, exps, 
     for lam in (0.2, 0.5, 0.7):
         for x, y in zip(w.wave2d_weights(sid, lam), w.wave2d_weights(ref, lam)):
             assert np.allclose(x, y, rtol=0, atol=1e-14)
+
+
+# ---- schemes with nodes up to three lines out --------------------------------
+
+ORC_DEG6 = 1001
+
+
+@pytest.fixture(scope="module")
+def deg6_oracle():
+    wts = derive.node_weights(28)
+    oracle.register_scheme(ORC_DEG6, wts)
+    return wts
+
+
+def test_library_degree6_set_weights(deg6_oracle):
+    """The complete degree-6 set (Q_28, M*_{<=28}): the library's floating
+    point construction equals the exact one on all nine classes; the old
+    three-class call refuses it instead of dropping classes."""
+    sid = w.wave2d_scheme_create(derive.stencil(28), derive.monomials(28))
+    for lam in (0.1, 0.35, 0.5):
+        w2, wa, wb = w.wave2d_class_weights(sid, lam)
+        for c, q in enumerate(w.CLASSES):
+            A, B = deg6_oracle.get(q, ({}, {}))
+            assert abs(wa[c] - derive.evaluate(A, lam)) < 1e-13, (q, lam)
+            assert abs(wb[c] - derive.evaluate(B, lam)) < 1e-13, (q, lam)
+            assert w2[c] == 2 * wa[c]
+        assert wa[4] == wa[6] == wa[7] == wa[8] == 0.0
+        assert wa[3] != 0.0 and wa[5] != 0.0
+    with pytest.raises(w.Wave2dError):
+        w.wave2d_weights(sid, 0.3)
+    with pytest.raises(w.Wave2dError):
+        w.wave2d_class_weights(sid, 0.3, nclass=5)
+    # the paper's schemes through the nine-class call: zeros beyond (2,0)
+    w2, wa, _ = w.wave2d_class_weights(w.P13, 0.5)
+    assert w2[3:] == [0.0] * 6 and w.wave2d_weights(w.P13, 0.5)[0] == w2[:3]
+
+
+def test_library_degree6_limit_against_brute_force_stepping(deg6_oracle):
+    """The symbol-based stability limit of the degree-6 scheme against the
+    oracle's own stepping on a periodic grid: bounded at 0.99 of it, blow-up
+    at 1.01."""
+    sid = w.wave2d_scheme_create(derive.stencil(28), derive.monomials(28))
+    lmax = w.wave2d_lambda_max(sid)
+    assert 0.3 < lmax < 1.0
+    assert _growth(ORC_DEG6, 0.99 * lmax) < 10.0
+    g = _growth(ORC_DEG6, 1.01 * lmax)
+    assert not np.isfinite(g) or g > 1e3
+
+
+def test_wide_schemes_outside_the_one_level_calls():
+    """Batches, the server and the tuning calls take the 5/9/13-point
+    classes only; a wide scheme gets EINVAL there (host checks, no GPU)."""
+    sid = w.wave2d_scheme_create(derive.stencil(28), derive.monomials(28))
+    with pytest.raises(w.Wave2dError) as e:
+        w.wave2d_get_tuning(w.F32C, sid, 100, 100)
+    assert e.value.status == EINVAL
