@@ -416,6 +416,71 @@ def off_table_bench(dev):
             "depth": depth, "rows": rows}
 
 
+def wide_bench(dev):
+    """A built scheme reaching three lines out (the complete degree-6 set of
+    Sec. 4-5, 25 nodes), 4097^2, 200 levels at 0.9 of its stability limit,
+    FP64 and compensated FP32: one level per launch through LDS-staged
+    tiles, 24 algorithmic bytes per update in both precisions (FP64: u^k and
+    u^{k-1} read, u^{k+1} written; compensated: u, lo, d read and written)."""
+    import torch
+
+    import oracle
+    import paper_1904_04048_amd as w
+    from oracle import derive
+    from paper_1904_04048_amd import workloads as W
+    sid = w.wave2d_scheme_create(derive.stencil(28), derive.monomials(28))
+    n, steps = 4097, 200
+    h = 1.0 / (n - 1)
+    tau = 0.9 * w.wave2d_lambda_max(sid) * h
+    modes = [(2, 3, 1.0, 0.0), (1, 1, 0.0, 1.0)]
+    U0, V0 = W.sine_series_torch(n, n, modes, dev)
+    lup = (n - 2) * (n - 2) * steps
+    P, C = torch.empty_like(U0), torch.empty_like(U0)
+    t64 = median_time(lambda: w.wave2d_run(U0, V0, P, C, h, tau, 1.0, sid, steps), 3)
+    u = torch.empty((n, n), dtype=torch.float32, device=dev)
+    lo, d = torch.empty_like(u), torch.empty_like(u)
+    work = torch.empty(w.wave2d_work_bytes(w.F32C, n, n), dtype=torch.uint8, device=dev)
+    t32 = median_time(lambda: w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, sid, steps, work=work), 3)
+    # Errors: compensated FP32 against the GPU FP64 path at full size (both
+    # after `steps` levels), and both paths against the oracle on a 257^2
+    # copy of the workload.
+    out = torch.empty_like(U0)
+    w.wave2d_f32c_export(u, lo, out)
+    f32_vs_f64 = float((out - C).abs().max() / C.abs().max())
+    # One level of the compensated kernel, timed with HIP events on the
+    # current stream (the state runs on past the compared level).
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    w.wave2d_f32c_step(u, lo, d, h, tau, 1.0, sid, 100, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_level = e0.elapsed_time(e1) / 1e3 / 100
+    m = 257
+    oracle.register_scheme(1010, derive.node_weights(28))
+    u0s, v0s = W.sine_series(m, m, modes)
+    hs = 1.0 / (m - 1)
+    taus = 0.9 * w.wave2d_lambda_max(sid) * hs
+    _, ref = oracle.run(u0s, v0s, hs, taus, 1.0, 1010, 400)
+    U0s, V0s = torch.from_numpy(u0s).to(dev), torch.from_numpy(v0s).to(dev)
+    us = torch.empty((m, m), dtype=torch.float32, device=dev)
+    los, ds = torch.empty_like(us), torch.empty_like(us)
+    w.wave2d_f32c_run(U0s, V0s, us, los, ds, hs, taus, 1.0, sid, 400)
+    outs = torch.empty_like(U0s)
+    w.wave2d_f32c_export(us, los, outs)
+    Ps, Cs = torch.empty_like(U0s), torch.empty_like(U0s)
+    w.wave2d_run(U0s, V0s, Ps, Cs, hs, taus, 1.0, sid, 400)
+    alg = STATE_BYTES_PER_NODE * n * n
+    return {"workload": "built scheme, complete degree-6 set (25 nodes, radius 3), 4097x4097, 200 levels",
+            "value": round(lup / t32 / 1e9, 2), "unit": "GLUP/s", "ms_per_solve": round(t32 * 1e3, 2),
+            "fp64_value": round(lup / t64 / 1e9, 2), "fp64_ms_per_solve": round(t64 * 1e3, 2),
+            "roofline": roofline_hbm(alg, t_level, (n - 2) * (n - 2), None,
+                                     "k_wide_step_f32c (one level per launch)", {}),
+            "error": {"max_rel_f32c_vs_gpu_fp64": f32_vs_f64,
+                      "copy_257_400_levels": {"max_rel_f32c_vs_oracle": oracle.rel_max_err(outs.cpu().numpy(), ref),
+                                              "max_rel_fp64_vs_oracle": oracle.rel_max_err(Cs.cpu().numpy(), ref)}}}
+
+
 # ---- served workload ------------------------------------------------------------
 
 def serve_bench(args):
@@ -843,6 +908,8 @@ def main():
         torch.cuda.empty_cache()
         single["c1_5pt_257_fp64"] = c1_bench(dev)
         single["off_table_9pt_6001"] = off_table_bench(dev)
+        torch.cuda.empty_cache()
+        single["wide_deg6_4097"] = wide_bench(dev)
         torch.cuda.empty_cache()
         out["single_grid"] = single
     if not args.no_serve:

@@ -1,10 +1,11 @@
 // Kernels for schemes whose stencil reaches up to three lines from the
 // centre: the schemes that the construction of Sec. 4-5 builds from larger
 // monomial sets (the complete set of degree 6 weights the classes (2,1) and
-// (3,0) besides the 13-point ones).  One node per thread and one level per
-// launch: a 64 x 8 block stages its tile of the level, with a halo of three
-// nodes on every side, in LDS (the boundary rule applied while loading), and
-// every node of the block then forms its class sums from LDS.
+// (3,0) besides the 13-point ones).  One level per launch: a block of 64 x 8
+// threads stages its 64 x 32 tile of the level, with a halo of three nodes
+// on every side, in LDS (the boundary rule applied while loading, plain
+// loads for tiles inside the grid), and each thread then forms the class
+// sums of four nodes of one column from LDS.
 //
 // Node classes (q1, q2), q1 >= q2 >= 0, in this order: (1,0), (1,1), (2,0),
 // (2,1), (2,2), (3,0), (3,1), (3,2), (3,3).  A class holds the rotations of
@@ -16,8 +17,9 @@
 namespace w2d {
 namespace {
 
-constexpr int WX = 64, WY = 8, HALO = 3;
-constexpr int TX = WX + 2 * HALO, TY = WY + 2 * HALO;
+constexpr int WX = 64, WY = 8, RPT = 4, HALO = 3;  // threads x, y; rows per thread
+constexpr int BH = WY * RPT;                        // rows per block
+constexpr int TX = WX + 2 * HALO, TY = BH + 2 * HALO;
 constexpr int kQ[kWideClasses][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}, {3, 0}, {3, 1}, {3, 2}, {3, 3}};
 
 // Value of node (i, j) under the boundary rule, for (i, j) up to three
@@ -47,14 +49,28 @@ __device__ __forceinline__ T wide_load(const T* __restrict__ p, const Grid& g, i
 }
 
 // Stage the block's tile (block origin x0, y0; tile origin three nodes
-// above and to the left) of one field in LDS.
+// above and to the left) of one field in LDS.  A tile whose nodes are all
+// read as stored (inside the grid, off its boundary under the Dirichlet
+// rule) is loaded without the boundary rule; the choice is the same for
+// every thread of the block.
 template <typename T>
 __device__ __forceinline__ void load_tile(T (*t)[TX], const T* __restrict__ p, const Grid& g, int x0, int y0)
 {
-    const int tid = threadIdx.y * WX + threadIdx.x;
-    for (int k = tid; k < TX * TY; k += WX * WY) {
-        const int ty = k / TX, tx = k - ty * TX;
-        t[ty][tx] = wide_load(p, g, x0 - HALO + tx, y0 - HALO + ty);
+    const int xa = x0 - HALO, ya = y0 - HALO;
+    const int lo = g.periodic ? 0 : 1;
+    const bool plain = xa >= lo && ya >= lo && xa + TX - 1 <= g.nx - 1 - lo && ya + TY - 1 <= g.ny - 1 - lo;
+    const int tx0 = threadIdx.x, tx1 = threadIdx.x + WX;
+    if (plain) {
+        const T* q = p + (size_t)ya * g.ld + xa;
+        for (int ty = threadIdx.y; ty < TY; ty += WY) {
+            t[ty][tx0] = q[(size_t)ty * g.ld + tx0];
+            if (tx1 < TX) t[ty][tx1] = q[(size_t)ty * g.ld + tx1];
+        }
+    } else {
+        for (int ty = threadIdx.y; ty < TY; ty += WY) {
+            t[ty][tx0] = wide_load(p, g, xa + tx0, ya + ty);
+            if (tx1 < TX) t[ty][tx1] = wide_load(p, g, xa + tx1, ya + ty);
+        }
     }
 }
 
@@ -115,52 +131,65 @@ __global__ __launch_bounds__(WX* WY) void k_wide_first(Grid g, WideFirstW w, con
                                                        float* __restrict__ d)
 {
     __shared__ double ta[TY][TX], tb[TY][TX];
-    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * WY;
+    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * BH;
     load_tile(ta, u0, g, x0, y0);
     if (w.poisson) load_tile(tb, v0, g, x0, y0);
     __syncthreads();
-    const int i = x0 + threadIdx.x, j = y0 + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
-    const int ly = threadIdx.y + HALO, lx = threadIdx.x + HALO;
-    double r = 0.0, prev = 0.0;
-    if (wide_interior(g, i, j)) {
-        const double c = ta[ly][lx];
-        const double sa = wide_sum(ta, ly, lx, w.a, 0.0);
-        const double sb = w.poisson ? wide_sum(tb, ly, lx, w.b, 0.0) : 0.0;
-        r = first_update(c, sa, v0[(size_t)j * g.ld + i], sb, w.tau);
-        prev = c;
-    }
-    const size_t o = (size_t)j * g.ld + i;
-    if constexpr (F32C) {
-        float ru = 0.f, rl = 0.f, rd = 0.f;
-        if (wide_interior(g, i, j)) f32c_split(r, prev, ru, rl, rd);
-        u[o] = ru;
-        lo[o] = rl;
-        d[o] = rd;
-    } else {
-        u1[o] = r;
+    const int i = x0 + threadIdx.x;
+    if (i >= g.nx) return;
+    const int lx = threadIdx.x + HALO;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ry = threadIdx.y * RPT + k, j = y0 + ry;
+        if (j >= g.ny) break;
+        const int ly = ry + HALO;
+        double r = 0.0, prev = 0.0;
+        const bool in = wide_interior(g, i, j);
+        if (in) {
+            const double c = ta[ly][lx];
+            const double sa = wide_sum(ta, ly, lx, w.a, 0.0);
+            const double sb = w.poisson ? wide_sum(tb, ly, lx, w.b, 0.0) : 0.0;
+            r = first_update(c, sa, v0[(size_t)j * g.ld + i], sb, w.tau);
+            prev = c;
+        }
+        const size_t o = (size_t)j * g.ld + i;
+        if constexpr (F32C) {
+            float ru = 0.f, rl = 0.f, rd = 0.f;
+            if (in) f32c_split(r, prev, ru, rl, rd);
+            u[o] = ru;
+            lo[o] = rl;
+            d[o] = rd;
+        } else {
+            u1[o] = r;
+        }
     }
 }
 
 // FP64 two-step update (eq. A2).  u_next may equal u_prev: each thread reads
-// its own node of u_prev before writing it, and never reads other nodes of
-// it.
+// its own nodes of u_prev before writing them, and never reads other nodes
+// of it.
 __global__ __launch_bounds__(WX* WY) void k_wide_step_f64(Grid g, WideW64 w, const double* u_prev,
                                                           const double* __restrict__ u_cur, double* u_next)
 {
     __shared__ double t[TY][TX];
-    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * WY;
+    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * BH;
     load_tile(t, u_cur, g, x0, y0);
     __syncthreads();
-    const int i = x0 + threadIdx.x, j = y0 + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
-    const size_t o = (size_t)j * g.ld + i;
-    double r = 0.0;
-    if (wide_interior(g, i, j)) {
-        const int ly = threadIdx.y + HALO, lx = threadIdx.x + HALO;
-        r = f64_update(t[ly][lx], u_prev[o], wide_sum(t, ly, lx, w.w, 0.0));
+    const int i = x0 + threadIdx.x;
+    if (i >= g.nx) return;
+    const int lx = threadIdx.x + HALO;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ry = threadIdx.y * RPT + k, j = y0 + ry;
+        if (j >= g.ny) break;
+        const size_t o = (size_t)j * g.ld + i;
+        double r = 0.0;
+        if (wide_interior(g, i, j)) {
+            const int ly = ry + HALO;
+            r = f64_update(t[ly][lx], u_prev[o], wide_sum(t, ly, lx, w.w, 0.0));
+        }
+        u_next[o] = r;
     }
-    u_next[o] = r;
 }
 
 // Compensated FP32 two-step update: (u, lo, d) -> (u2, lo2, d2).
@@ -170,25 +199,31 @@ __global__ __launch_bounds__(WX* WY) void k_wide_step_f32c(Grid g, WideW32 w, co
                                                            float* __restrict__ lo2, float* __restrict__ d2)
 {
     __shared__ float tu[TY][TX], tl[TY][TX];
-    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * WY;
+    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * BH;
     load_tile(tu, u, g, x0, y0);
     load_tile(tl, lo, g, x0, y0);
     __syncthreads();
-    const int i = x0 + threadIdx.x, j = y0 + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
-    const size_t o = (size_t)j * g.ld + i;
-    float ru = 0.f, rl = 0.f, rd = 0.f;
-    if (wide_interior(g, i, j)) {
-        const int ly = threadIdx.y + HALO, lx = threadIdx.x + HALO;
-        const float s = wide_sum_f32c(tu, tl, ly, lx, w.w, w.wl, 0.f);
-        f32c_update(s, tu[ly][lx], tl[ly][lx], d[o], ru, rl, rd);
+    const int i = x0 + threadIdx.x;
+    if (i >= g.nx) return;
+    const int lx = threadIdx.x + HALO;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ry = threadIdx.y * RPT + k, j = y0 + ry;
+        if (j >= g.ny) break;
+        const size_t o = (size_t)j * g.ld + i;
+        float ru = 0.f, rl = 0.f, rd = 0.f;
+        if (wide_interior(g, i, j)) {
+            const int ly = ry + HALO;
+            const float s = wide_sum_f32c(tu, tl, ly, lx, w.w, w.wl, 0.f);
+            f32c_update(s, tu[ly][lx], tl[ly][lx], d[o], ru, rl, rd);
+        }
+        u2[o] = ru;
+        lo2[o] = rl;
+        d2[o] = rd;
     }
-    u2[o] = ru;
-    lo2[o] = rl;
-    d2[o] = rd;
 }
 
-dim3 wide_grid(const Grid& g) { return dim3((g.nx + WX - 1) / WX, (g.ny + WY - 1) / WY); }
+dim3 wide_grid(const Grid& g) { return dim3((g.nx + WX - 1) / WX, (g.ny + BH - 1) / BH); }
 
 }  // namespace
 
