@@ -287,6 +287,11 @@ def wave2d_server_submit(server, nx, ny, h, tau, c, scheme, steps, flags=0, mode
     else:
         rq.u0 = u0.data_ptr() if u0 is not None else None
         rq.v0 = v0.data_ptr() if v0 is not None else None
+        if u0 is not None or v0 is not None:
+            # The server reads the grids on its own stream: work queued on
+            # this one that writes them must be complete first.
+            import torch
+            torch.cuda.current_stream().synchronize()
     rid = ctypes.c_uint64()
     _lib.check(_lib.load().wave2d_server_submit(server, ctypes.byref(rq), ctypes.byref(rid)))
     return rid.value
