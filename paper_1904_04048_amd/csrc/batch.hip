@@ -89,7 +89,8 @@ struct wave2d_batch {
     // and item counts, and its counter block (n_ctr ints each).
     size_t p_insts = 0, p_tasks = 0, p_qoff[kClasses] = {}, p_qn[kClasses] = {}, p_ctr[kClasses] = {};
     bool p_has[kClasses] = {};
-    int n_ctr = 0;
+    int n_ctr[kClasses] = {};         // counters per class: heads, stalls, tiles
+    std::vector<int> tile_off;        // per instance, within its class's tile counters
     long long wait_ticks = kWaitTicks;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the persistent launches
     // The stencil classes' persistent launches run concurrently: the first
@@ -184,21 +185,27 @@ struct PersistPlan {
 // The invariants the persistent kernel relies on: per class and queue, the
 // tasks [qoff[q], qoff[q+1]) cover items 0 .. qn[q]-1 in order (each task's
 // first item is the previous task's end), every task's instance belongs to
-// the class, and its wait count is a whole number of that instance's passes.
+// the class, and each instance's passes appear in order 0, 1, ..., once
+// each (a pass waits only for passes queued before it).
 int check_plan(const wave2d_batch* b, const PersistPlan& pl, const std::vector<int>& items)
 {
+    std::vector<int64_t> seen(b->inst.size(), 0);
     for (int c = 0; c < kClasses; ++c)
         for (int q = 0; q < kPersistQueues; ++q) {
             int64_t next = 0;
             for (int t = pl.qoff[c][q]; t < pl.qoff[c][q + 1]; ++t) {
                 const PersistTask& k = pl.tasks[(size_t)t];
                 if (k.inst < 0 || (size_t)k.inst >= b->inst.size() || b->inst[(size_t)k.inst].p.kind != c ||
-                    k.first != next || items[(size_t)k.inst] < 1 || k.need % items[(size_t)k.inst] != 0)
+                    k.first != next || items[(size_t)k.inst] < 1 || k.pass != seen[(size_t)k.inst])
                     return fail(WAVE2D_EDEVICE, "persistent plan inconsistent at class %d queue %d task %d", c, q, t);
+                ++seen[(size_t)k.inst];
                 next += items[(size_t)k.inst];
             }
             if (next != pl.qn[c][q]) return fail(WAVE2D_EDEVICE, "persistent plan: queue %d item count", q);
         }
+    for (size_t i = 0; i < b->inst.size(); ++i)
+        if (seen[i] != b->full[i]) return fail(WAVE2D_EDEVICE, "persistent plan: instance %zu has %lld of %lld passes", i,
+                                                (long long)seen[i], (long long)b->full[i]);
     return WAVE2D_OK;
 }
 
@@ -218,8 +225,11 @@ int plan_persist(const wave2d_batch* b, int cap, PersistPlan* pl)
         int nb = 0, rows_used = 0;
         const int D = persist_depth(rc.p.kind);
         const int R = rc.p.kind == KIND13 ? 2 : 1;
-        items[i] = persist_inst(rc.p.g, rc.p.kind, step_w32(rc.p), persist_rows(rc.p.g.ny, cap), s0, s1,
-                                pl->recs.data() + i * isz, &nb, &rows_used);
+        items[i] = persist_inst(rc.p.g, rc.p.kind, step_w32(rc.p), persist_rows(rc.p.g.ny, cap), b->tile_off[i], s0,
+                                s1, pl->recs.data() + i * isz, &nb, &rows_used);
+        if (items[i] < 1)
+            return fail(WAVE2D_EINVAL, "instance %zu: segments of %d rows leave too many tiles", i,
+                        persist_rows(rc.p.g.ny, cap));
         // Work model: an item streams rows + R (D - 1) + 2R + 1 rows of D
         // levels, each about 2R + 1 times the 5-point work.
         cost[i] = (double)b->full[i] * items[i] * (rows_used + R * (D - 1) + 2 * R + 1) * D * (2 * R + 1);
@@ -244,16 +254,24 @@ int plan_persist(const wave2d_batch* b, int cap, PersistPlan* pl)
         pl->qn[c].assign(kPersistQueues, 0);
         for (int q = 0; q < kPersistQueues; ++q) {
             pl->qoff[c][q] = (int)pl->tasks.size();
-            int64_t maxp = 0;
-            for (size_t i : members[q]) maxp = std::max(maxp, b->full[i]);
+            // Passes in order of the progress they complete, (p + 1) /
+            // full: every instance advances at the same relative pace, so
+            // instances with many passes are not left alone at the end of
+            // the queue as chains of small passes that cannot fill the XCC.
+            struct Key {
+                double prog;
+                size_t i;
+                int64_t p;
+            };
+            std::vector<Key> keys;
+            for (size_t i : members[q])
+                for (int64_t p = 0; p < b->full[i]; ++p) keys.push_back(Key{(double)(p + 1) / (double)b->full[i], i, p});
+            std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) { return x.prog < y.prog; });
             int64_t first = 0;
-            for (int64_t p = 0; p < maxp; ++p)
-                for (size_t i : members[q]) {
-                    if (p >= b->full[i]) continue;
-                    pl->tasks.push_back(
-                        PersistTask{(int)i, (int)((b->par0[i] + p) & 1), (int)(p * items[i]), (int)first});
-                    first += items[i];
-                }
+            for (const Key& k : keys) {
+                pl->tasks.push_back(PersistTask{(int)k.i, (int)((b->par0[k.i] + k.p) & 1), (int)k.p, (int)first});
+                first += items[k.i];
+            }
             if (first >= (int64_t(1) << 31))
                 return fail(WAVE2D_EINVAL, "batch too large for one persistent launch (%lld items on one XCC)",
                             (long long)first);
@@ -270,7 +288,7 @@ int enqueue(wave2d_batch* b, hipStream_t s, bool timing)
 {
     char* base = (char*)b->tables;
     for (int c = 0; c < kClasses; ++c)
-        if (b->p_has[c]) W2D_HIP(fill_i32((int*)(base + b->p_ctr[c]), b->n_ctr, 0, s));
+        if (b->p_has[c]) W2D_HIP(fill_i32((int*)(base + b->p_ctr[c]), b->n_ctr[c], 0, s));
     // First steps (fused with the state split) of every instance: one launch.
     W2D_HIP(first_step_f32c_batch((const FirstRecF32C*)(base + b->first_recs), (const int*)(base + b->first_prefix),
                                   b->first_count, b->first_blocks, s));
@@ -545,9 +563,27 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
         b->rounds.push_back(rd);
     }
 
-    // The persistent launch: instance records, per-XCC task queues.
+    // The persistent launch: instance records, per-XCC task queues, and the
+    // tile counters of each class (every instance of a class gets a block
+    // sized for its smallest segments, so that re-planning for another
+    // segment height keeps the layout).
     if (b->persist) {
         b->full = full;
+        b->tile_off.assign(ni, 0);
+        int64_t tiles[kClasses] = {};
+        for (size_t i = 0; i < ni; ++i) {
+            const int c = b->inst[i].p.kind;
+            b->tile_off[i] = (int)tiles[c];
+            tiles[c] += persist_max_tiles(b->inst[i].p.g, c);
+        }
+        for (int c = 0; c < kClasses; ++c) {
+            if (kPersistTileBase + tiles[c] >= (int64_t(1) << 30)) {
+                (void)hipFree(b->work);
+                delete b;
+                return fail(WAVE2D_EINVAL, "batch too large for one persistent launch (%lld tiles)", (long long)tiles[c]);
+            }
+            b->n_ctr[c] = kPersistTileBase + (int)tiles[c];
+        }
         b->par0.assign(ni, 0);
         for (size_t i = 0; i < ni; ++i) {
             b->par0[i] = in_b[i] ? 1 : 0;
@@ -564,12 +600,11 @@ int wave2d_batch_create(const wave2d_instance* inst, int64_t count, uint32_t fla
         } else {
             b->p_insts = put(pl.recs.data(), pl.recs.size());
             b->p_tasks = put(pl.tasks.data(), pl.tasks.size() * sizeof(PersistTask));
-            b->n_ctr = persist_counters((int)ni);
-            std::vector<int> zeros(b->n_ctr, 0);
             for (int c = 0; c < kClasses; ++c) {
                 b->p_has[c] = pl.qoff[c][kPersistQueues] > pl.qoff[c][0];
                 b->p_qoff[c] = put(pl.qoff[c].data(), pl.qoff[c].size() * sizeof(int));
                 b->p_qn[c] = put(pl.qn[c].data(), pl.qn[c].size() * sizeof(int));
+                const std::vector<int> zeros((size_t)b->n_ctr[c], 0);
                 b->p_ctr[c] = put(zeros.data(), zeros.size() * sizeof(int));
             }
             b->st.items += pl.items;

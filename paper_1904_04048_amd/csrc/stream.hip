@@ -819,11 +819,16 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const
 // complex die (XCC, an L2 domain) and lists, per XCC, the instances' passes
 // in pass-major order as tasks of one work item per wave.  A wave reads the
 // id of the XCC it runs on, takes the next item of that XCC's queue (an
-// atomic counter) and, before running it, waits until every item of the
-// instance's previous pass is done (a per-instance counter of finished
-// items).  Items are taken in queue order, so every item a wave waits for
-// was taken earlier by a running wave, and the earliest unfinished item
-// never waits: the queue always drains.
+// atomic counter) and, before running it, waits until the tiles whose
+// output it reads have finished the previous pass: the item's own tile
+// (strip x segment) and its neighbours, one strip to each side and `kr`
+// segments up and down (enough for the rows and columns a pass reads
+// beyond its outputs; wrapped on periodic grids).  Each tile keeps a counter
+// of its finished passes.  The same wait orders the writes of the next pass
+// after the reads of the previous one: a tile's pass p+1 overwrites the
+// state that the neighbours' pass p read.  Items are taken in queue order,
+// so every item a wave waits for was taken earlier by a running wave, and
+// the earliest unfinished item never waits: the queue always drains.
 //
 // Every item of an instance runs on the one XCC its queue belongs to, so
 // all of an instance's traffic inside the launch goes through one L2, the
@@ -842,8 +847,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const
 // L1 stale and got about 20 instances wrong per run, as did dropping the
 // invalidation.
 // Two passes apart an instance writes the state it read one pass earlier;
-// the per-pass wait orders that too (pass p+1 starts after every item of
-// pass p, the last readers of the state it overwrites, is done).
+// the neighbour wait orders that too (see above).
 //
 // Every wave-level decision is made by all 64 lanes on identical values
 // (atomics are issued by every lane with the increment carried by the first
@@ -856,7 +860,21 @@ struct PInst {
     Decomp dc;
     StepW32 w;
     int kind, nb, items;
+    int tile_off;  // first tile counter of the instance (after kPersistTileBase)
+    int kr;        // neighbour segments to wait for on each side
 };
+
+// Strip and segment of work item `wid` of a pass (boundary items first).
+__device__ __forceinline__ void item_tile(const Decomp& dc, int nb, int wid, int& strip, int& seg)
+{
+    if (wid < nb) {
+        boundary_item(dc, wid, strip, seg);
+    } else {
+        const int k = wid - nb;
+        strip = dc.s_lo + k % dc.ns;
+        seg = dc.g_lo + k / dc.ns;
+    }
+}
 
 // The XCC the calling wave runs on (hardware register XCC_ID, low 4 bits).
 __device__ __forceinline__ int xcc_id()
@@ -892,7 +910,6 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
     const int total = qn[q];
     int* head = ctr + kPersistStride * q;
     int* stalls = ctr + kPersistStride * kPersistQueues;
-    int* done = ctr + kPersistStride * (kPersistQueues + 1);
     for (;;) {
         const int k = wave_fetch_inc(head);
         if (k >= total) break;
@@ -903,10 +920,31 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
             else hi = mid - 1;
         }
         const PersistTask t = tasks[lo];
-        int* cnt = done + kPersistStride * t.inst;
-        bool ok = true;
-        if (t.need > 0) {
-            if (wave_load(cnt) < t.need) {
+        const PInst& pi = insts[t.inst];
+        const Decomp dc = pi.dc;
+        const int wid = k - t.first;
+        // A work id outside the task (tables out of step with the queue)
+        // is skipped and reported instead of being run.
+        bool ok = k >= t.first && wid < pi.items;
+        int strip = 0, seg = 0;
+        if (ok) item_tile(dc, pi.nb, wid, strip, seg);
+        int* tiles = ctr + kPersistTileBase + pi.tile_off;
+        if (t.pass > 0) {
+            // Lane l watches neighbour (strip + l % 3 - 1, seg + l / 3 - kr);
+            // lanes past the neighbourhood, and neighbours off a Dirichlet
+            // grid, watch the item's own tile.
+            const int lane = (int)(threadIdx.x & (kWave - 1));
+            const int kr = pi.kr, nst = dc.nstrips, nsg = dc.nseg;
+            int sn = strip + lane % 3 - 1, gn = seg + lane / 3 - kr;
+            bool use = lane < 3 * (2 * kr + 1);
+            if (pi.a[0].g.periodic) {
+                sn = ((sn % nst) + nst) % nst;
+                gn = ((gn % nsg) + nsg) % nsg;
+            } else {
+                use = use && sn >= 0 && sn < nst && gn >= 0 && gn < nsg;
+            }
+            const int* watch = tiles + (use ? gn * nst + sn : seg * nst + strip);
+            if (!__all(__hip_atomic_load(watch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= t.pass)) {
                 // Poll with a growing pause (up to 64 x 512 cycles); give up
                 // after wait_ticks of the 100 MHz real-time clock, or at once
                 // when another wait of this launch has given up.
@@ -915,7 +953,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
                 for (int polls = 1;; ++polls) {
                     for (int z = 0; z < pause; ++z) __builtin_amdgcn_s_sleep(8);
                     pause = min(2 * pause, 64);
-                    if (wave_load(cnt) >= t.need) break;
+                    if (__all(__hip_atomic_load(watch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= t.pass)) break;
                     if ((polls & 7) == 0 && wave_load(stalls) > 0) {
                         ok = false;
                         break;
@@ -930,26 +968,21 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
             // lines of the state the previous pass rewrote.
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        // A work id outside the task (tables out of step with the queue)
-        // is skipped and reported instead of being run.
-        if (ok && (k < t.first || k - t.first >= insts[t.inst].items)) ok = false;
         if (ok) {
-            const PInst& pi = insts[t.inst];
             const SArgs<float> a = pi.a[t.par];
-            const Decomp dc = pi.dc;
             const StepW32 w = pi.w;
             const int nb = pi.nb;
-            const int wid = k - t.first;
             if (wid < nb) stream_body<PF32C, K, DEPTH, 2, true>(a, dc, wid, w);
             else stream_body<PF32C, K, DEPTH, 2, false>(a, dc, wid - nb, w);
         } else {
             (void)wave_fetch_inc(stalls);
         }
         // The item's loads are done and its stores are in this XCC's L2
-        // before it is counted done (the memory clobber keeps the compiler
-        // from moving memory operations across the wait).
+        // before its tile is counted (the memory clobber keeps the compiler
+        // from moving memory operations across the wait).  A skipped item
+        // counts too, so that the items waiting for it end.
         asm volatile("s_waitcnt vmcnt(0) expcnt(0) lgkmcnt(0)" ::: "memory");
-        (void)wave_fetch_inc(cnt);
+        (void)wave_fetch_inc(tiles + seg * dc.nstrips + strip);
     }
 }
 
@@ -1292,13 +1325,29 @@ hipError_t blaunch_prec(int kind, int depth, bool interior, const void* items, c
 constexpr int kPD5 = 8, kPD9 = 8, kPD13 = 6;
 
 template <int K, int DEPTH>
-int persist_inst_k(const Grid& g, const StepW32& w, int rows, float* const s0[3], float* const s1[3],
-                   unsigned char* rec, int* nb, int* rows_used)
+int persist_max_tiles_k(const Grid& g)
 {
     constexpr int R = KT<K>::R;
+    const Decomp dc = make_decomp<R, DEPTH, 2>(g, kPersistMinRows);
+    return dc.nstrips * dc.nseg;
+}
+
+template <int K, int DEPTH>
+int persist_inst_k(const Grid& g, const StepW32& w, int rows, int tile_off, float* const s0[3],
+                   float* const s1[3], unsigned char* rec, int* nb, int* rows_used)
+{
+    constexpr int R = KT<K>::R;
+    constexpr int NS = 2 * R + 1, H = R * DEPTH;
     PInst p{};
     rows = fit_rows<R, DEPTH>(g, rows, sizeof(float));
     const Decomp dc = make_decomp<R, DEPTH, 2>(g, rows);
+    if (dc.nstrips * dc.nseg > persist_max_tiles_k<K, DEPTH>(g)) return -1;
+    // An item reads rows y0 - H - NS .. y1 + H + 2 NS of its input: the
+    // segments within 1 + (H + 2 NS) / rows of its own on either side.  Its
+    // columns reach HP < SW beyond its strip: one strip on either side.
+    p.kr = 1 + (H + 2 * NS) / rows;
+    if (3 * (2 * p.kr + 1) > kWave) return -1;
+    p.tile_off = tile_off;
     for (int par = 0; par < 2; ++par) {
         SArgs<float>& a = p.a[par];
         float* const* in = par ? s1 : s0;
@@ -1343,13 +1392,22 @@ size_t persist_inst_size() { return sizeof(PInst); }
 
 int persist_depth(int kind) { return kind == KIND5 ? kPD5 : kind == KIND9 ? kPD9 : kPD13; }
 
-int persist_inst(const Grid& g, int kind, const StepW32& w, int rows, float* const s0[3], float* const s1[3],
-                 unsigned char* rec, int* nb, int* rows_used)
+int persist_inst(const Grid& g, int kind, const StepW32& w, int rows, int tile_off, float* const s0[3],
+                 float* const s1[3], unsigned char* rec, int* nb, int* rows_used)
 {
     switch (kind) {
-    case KIND5: return persist_inst_k<KIND5, kPD5>(g, w, rows, s0, s1, rec, nb, rows_used);
-    case KIND9: return persist_inst_k<KIND9, kPD9>(g, w, rows, s0, s1, rec, nb, rows_used);
-    default: return persist_inst_k<KIND13, kPD13>(g, w, rows, s0, s1, rec, nb, rows_used);
+    case KIND5: return persist_inst_k<KIND5, kPD5>(g, w, rows, tile_off, s0, s1, rec, nb, rows_used);
+    case KIND9: return persist_inst_k<KIND9, kPD9>(g, w, rows, tile_off, s0, s1, rec, nb, rows_used);
+    default: return persist_inst_k<KIND13, kPD13>(g, w, rows, tile_off, s0, s1, rec, nb, rows_used);
+    }
+}
+
+int persist_max_tiles(const Grid& g, int kind)
+{
+    switch (kind) {
+    case KIND5: return persist_max_tiles_k<KIND5, kPD5>(g);
+    case KIND9: return persist_max_tiles_k<KIND9, kPD9>(g);
+    default: return persist_max_tiles_k<KIND13, kPD13>(g);
     }
 }
 

@@ -148,26 +148,35 @@ ShapeFit stream_shape_fit(int precision, int kind, int depth);
 // One launch runs all passes of many compensated instances: one work queue
 // per XCC (instances pinned to one XCC), tasks of one item per wave.
 constexpr int kPersistQueues = 8;
-// Counters of a persistent launch, one per 128-byte line (kPersistStride
-// ints apart): queue heads 0..7, then the count of waits that gave up, then
-// the finished items of each instance.  All zero before the launch.
+// Counters of a persistent launch: queue heads 0..7 and the count of waits
+// that gave up, one per 128-byte line (kPersistStride ints apart), then one
+// counter per tile (strip x segment) of every instance of the launch, the
+// passes that tile has finished.  All zero before the launch.
 constexpr int kPersistStride = 32;
-inline int persist_counters(int instances) { return kPersistStride * (kPersistQueues + 1 + instances); }
-// Items [first, first + items) of a queue: pass `par` parity of instance
-// `inst`, runnable once `need` items of the instance are done.
+constexpr int kPersistTileBase = kPersistStride * (kPersistQueues + 1);
+// Segments of a persistent item have at least this many rows (fewer only
+// when the grid has fewer), which bounds an instance's tiles.
+constexpr int kPersistMinRows = 8;
+// Items [first, first + items) of a queue: pass number `pass` (parity
+// `par` of the state it reads) of instance `inst`.  An item runs once every
+// tile whose output it reads has finished `pass` passes.
 struct PersistTask {
-    int inst, par, need, first;
+    int inst, par, pass, first;
 };
 size_t persist_inst_size();
 // Pass depth of the persistent kernel for a stencil class.
 int persist_depth(int kind);
+// Most tiles an instance of the class can have (segments of
+// kPersistMinRows rows): the size of its block of tile counters.
+int persist_max_tiles(const Grid& g, int kind);
 // Write the device record of one instance into rec (persist_inst_size()
 // bytes): grid, class, weights, states s0 (u, lo, d) and s1 (the second
-// state), segment height `rows` (clamped like single-grid passes).  Returns
-// its work items per pass; *nb = how many of them are boundary items,
-// *rows_used = the height applied.
-int persist_inst(const Grid& g, int kind, const StepW32& w, int rows, float* const s0[3], float* const s1[3],
-                 unsigned char* rec, int* nb, int* rows_used);
+// state), segment height `rows` (clamped like single-grid passes), and the
+// offset of its tile counters.  Returns its work items per pass (-1 when
+// the clamped height leaves more tiles than persist_max_tiles); *nb = how
+// many of them are boundary items, *rows_used = the height applied.
+int persist_inst(const Grid& g, int kind, const StepW32& w, int rows, int tile_off, float* const s0[3],
+                 float* const s1[3], unsigned char* rec, int* nb, int* rows_used);
 // Workgroups of one persistent launch of a class (the kernel's resident
 // capacity).
 int persist_blocks(int kind);
