@@ -32,9 +32,29 @@ __device__ __forceinline__ T bc_load(const T* __restrict__ p, const Grid& g, int
     return neg ? -v : v;
 }
 
-template <int K, typename T>
+// Plain load of a node that the boundary rule leaves as stored.
+template <typename T>
+__device__ __forceinline__ T plain_load(const T* __restrict__ p, const Grid& g, int i, int j)
+{
+    return p[(size_t)j * g.ld + i];
+}
+
+// Whether every node within `r` of the BX x BY tile at (i0, j0) reads as
+// stored (inside the grid, off its boundary under the Dirichlet rule), so
+// that the tile can gather without the boundary rule.
+__device__ __forceinline__ bool plain_tile(const Grid& g, int i0, int j0, int r)
+{
+    const int lo = g.periodic ? 0 : 1;
+    return i0 - r >= lo && j0 - r >= lo && i0 + BX - 1 + r <= g.nx - 1 - lo && j0 + BY - 1 + r <= g.ny - 1 - lo;
+}
+
+template <int K, typename T, bool PLAIN = false>
 __device__ __forceinline__ Nbh<T> gather(const T* __restrict__ p, const Grid& g, int i, int j)
 {
+    auto bc_load = [&](const T* __restrict__ q, const Grid& gg, int ii, int jj) {
+        if constexpr (PLAIN) return plain_load(q, gg, ii, jj);
+        else return w2d::bc_load(q, gg, ii, jj);
+    };
     Nbh<T> v;
     v.C = bc_load(p, g, i, j);
     v.E = bc_load(p, g, i + 1, j);
@@ -84,16 +104,17 @@ __global__ __launch_bounds__(BX* BY) void k_first_step(Grid g, FirstW w, const d
     u1[(size_t)j * g.ld + i] = r;
 }
 
-// First step and split at node (i, j) (inside the grid).
-template <int K>
+// First step and split at node (i, j) (inside the grid); PLAIN: the
+// node's whole stencil reads as stored (see plain_tile).
+template <int K, bool PLAIN = false>
 __device__ __forceinline__ void first_node_f32c(const Grid& g, const FirstW& w, const double* __restrict__ u0,
                                                 const double* __restrict__ v0, float* __restrict__ u,
                                                 float* __restrict__ lo, float* __restrict__ d, int i, int j)
 {
     float ru = 0.f, rl = 0.f, rd = 0.f;
-    if (interior(g, i, j)) {
-        const Nbh<double> a = gather<K>(u0, g, i, j);
-        const Nbh<double> b = gather<K>(v0, g, i, j);
+    if (PLAIN || interior(g, i, j)) {
+        const Nbh<double> a = gather<K, double, PLAIN>(u0, g, i, j);
+        const Nbh<double> b = gather<K, double, PLAIN>(v0, g, i, j);
         const double sa = lap_diff<K>(a, w.a10, w.a11, w.a20);
         const double sb = w.poisson ? lap_diff<K>(b, w.b10, w.b11, w.b20) : 0.0;
         f32c_split(first_update(a.C, sa, b.C, sb, w.tau), a.C, ru, rl, rd);
@@ -137,12 +158,23 @@ __global__ __launch_bounds__(BX* BY) void k_first_step_f32c_batch(const FirstRec
     const FirstRecF32C rc = recs[r];
     const int t = b - prefix[r];
     const int tx = (rc.g.nx + BX - 1) / BX;
-    const int i = (t % tx) * BX + threadIdx.x, j = (t / tx) * BY + threadIdx.y;
+    const int i0 = (t % tx) * BX, j0 = (t / tx) * BY;
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= rc.g.nx || j >= rc.g.ny) return;
+    const bool plain = plain_tile(rc.g, i0, j0, rc.kind == KIND13 ? 2 : 1);
     switch (rc.kind) {
-    case KIND5: first_node_f32c<KIND5>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j); break;
-    case KIND9: first_node_f32c<KIND9>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j); break;
-    default: first_node_f32c<KIND13>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j); break;
+    case KIND5:
+        if (plain) first_node_f32c<KIND5, true>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j);
+        else first_node_f32c<KIND5>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j);
+        break;
+    case KIND9:
+        if (plain) first_node_f32c<KIND9, true>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j);
+        else first_node_f32c<KIND9>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j);
+        break;
+    default:
+        if (plain) first_node_f32c<KIND13, true>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j);
+        else first_node_f32c<KIND13>(rc.g, rc.w, rc.u0, rc.v0, rc.u, rc.lo, rc.d, i, j);
+        break;
     }
 }
 
