@@ -57,11 +57,7 @@ struct InstRec {
 // skipped and every later wait of the launch gives up at once, so a launch
 // always ends.  WAVE2D_BATCH_WAIT_MS overrides it (tests of that path).
 constexpr long long kWaitTicks = 200000000LL;
-constexpr int kClasses = 3;  // stencil classes KIND5, KIND9, KIND13: one persistent launch each
-
-// Tallest segment of a persistent work item (taller grids are cut into
-// equal segments of at most this many rows).
-constexpr int kPersistRowsCap = 160;
+constexpr int kClasses = kPersistClasses;  // stencil classes KIND5, KIND9, KIND13: one persistent launch each
 
 }  // namespace
 
@@ -130,156 +126,27 @@ int largest_supported(int d)
     return 1;
 }
 
-// Whether the workgroups of a launch land on exactly the kPersistQueues
-// XCCs 0..kPersistQueues-1 (one probe per device): the persistent kernel
-// keys its queues on them.
-bool xcc_layout_ok(int dev)
-{
-    static std::mutex mu;
-    static std::map<int, bool> cache;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(dev);
-    if (it != cache.end()) return it->second;
-    bool ok = false;
-    const int n = 64 * kPersistQueues;
-    int* d = nullptr;
-    if (hipMalloc(&d, n * sizeof(int)) == hipSuccess) {
-        std::vector<int> h(n, -1);
-        if (xcc_probe(d, n, nullptr) == hipSuccess &&
-            hipMemcpy(h.data(), d, n * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess) {
-            std::vector<int> cnt(kPersistQueues, 0);
-            ok = true;
-            for (int v : h) {
-                if (v < 0 || v >= kPersistQueues) ok = false;
-                else ++cnt[v];
-            }
-            for (int c : cnt) ok = ok && c > 0;
-        }
-        (void)hipFree(d);
-    }
-    (void)hipGetLastError();
-    cache[dev] = ok;
-    return ok;
-}
-
-// Segment height of an instance's persistent items: the whole grid up to
-// `cap` rows, else the grid cut into equal segments of at most `cap` rows.
-int persist_rows(int ny, int cap)
-{
-    if (ny <= cap) return ny;
-    const int nseg = (ny + cap - 1) / cap;
-    return (ny + nseg - 1) / nseg;
-}
-
-// Tables of the persistent launch for segments of at most `cap` rows:
-// instance records, tasks in per-queue pass-major order, queue offsets and
-// item counts (the layout does not depend on `cap`, only the contents).
-struct PersistPlan {
-    std::vector<unsigned char> recs;
-    std::vector<PersistTask> tasks;     // all classes, class by class
-    std::vector<int> qoff[kClasses];    // per class: task index ranges of the queues (absolute)
-    std::vector<int> qn[kClasses];      // per class: items per queue
-    int64_t items = 0, item_rows = 0;
-};
-
-// The invariants the persistent kernel relies on: per class and queue, the
-// tasks [qoff[q], qoff[q+1]) cover items 0 .. qn[q]-1 in order (each task's
-// first item is the previous task's end), every task's instance belongs to
-// the class, and each instance's passes appear in order 0, 1, ..., once
-// each (a pass waits only for passes queued before it).
-int check_plan(const wave2d_batch* b, const PersistPlan& pl, const std::vector<int>& items)
-{
-    std::vector<int64_t> seen(b->inst.size(), 0);
-    for (int c = 0; c < kClasses; ++c)
-        for (int q = 0; q < kPersistQueues; ++q) {
-            int64_t next = 0;
-            for (int t = pl.qoff[c][q]; t < pl.qoff[c][q + 1]; ++t) {
-                const PersistTask& k = pl.tasks[(size_t)t];
-                if (k.inst < 0 || (size_t)k.inst >= b->inst.size() || b->inst[(size_t)k.inst].p.kind != c ||
-                    k.first != next || items[(size_t)k.inst] < 1 || k.pass != seen[(size_t)k.inst])
-                    return fail(WAVE2D_EDEVICE, "persistent plan inconsistent at class %d queue %d task %d", c, q, t);
-                ++seen[(size_t)k.inst];
-                next += items[(size_t)k.inst];
-            }
-            if (next != pl.qn[c][q]) return fail(WAVE2D_EDEVICE, "persistent plan: queue %d item count", q);
-        }
-    for (size_t i = 0; i < b->inst.size(); ++i)
-        if (seen[i] != b->full[i]) return fail(WAVE2D_EDEVICE, "persistent plan: instance %zu has %lld of %lld passes", i,
-                                                (long long)seen[i], (long long)b->full[i]);
-    return WAVE2D_OK;
-}
-
 int plan_persist(const wave2d_batch* b, int cap, PersistPlan* pl)
 {
     const size_t ni = b->inst.size();
-    const size_t isz = persist_inst_size();
-    pl->recs.assign(ni * isz, 0);
-    pl->tasks.clear();
-    pl->items = pl->item_rows = 0;
-    std::vector<int> items(ni, 0);
-    std::vector<double> cost(ni, 0.0);
+    std::vector<PersistInput> in(ni);
     for (size_t i = 0; i < ni; ++i) {
         const InstRec& rc = b->inst[i];
-        float* s0[3] = {rc.in.u, rc.in.lo, rc.in.d};
-        float* s1[3] = {rc.bu, rc.bl, rc.bd};
-        int nb = 0, rows_used = 0;
-        const int D = persist_depth(rc.p.kind);
-        const int R = rc.p.kind == KIND13 ? 2 : 1;
-        items[i] = persist_inst(rc.p.g, rc.p.kind, step_w32(rc.p), persist_rows(rc.p.g.ny, cap), b->tile_off[i], s0,
-                                s1, pl->recs.data() + i * isz, &nb, &rows_used);
-        if (items[i] < 1)
-            return fail(WAVE2D_EINVAL, "instance %zu: segments of %d rows leave too many tiles", i,
-                        persist_rows(rc.p.g.ny, cap));
-        // Work model: an item streams rows + R (D - 1) + 2R + 1 rows of D
-        // levels, each about 2R + 1 times the 5-point work.
-        cost[i] = (double)b->full[i] * items[i] * (rows_used + R * (D - 1) + 2 * R + 1) * D * (2 * R + 1);
-        pl->items += b->full[i] * items[i];
-        pl->item_rows += b->full[i] * items[i] * (int64_t)rows_used;
+        PersistInput& x = in[i];
+        x.g = rc.p.g;
+        x.kind = rc.p.kind;
+        x.w = step_w32(rc.p);
+        x.s0[0] = rc.in.u;
+        x.s0[1] = rc.in.lo;
+        x.s0[2] = rc.in.d;
+        x.s1[0] = rc.bu;
+        x.s1[1] = rc.bl;
+        x.s1[2] = rc.bd;
+        x.tile_off = b->tile_off[i];
+        x.passes = b->full[i];
+        x.par0 = b->par0[i];
     }
-    // Per class, pin instances to queues: largest work first onto the
-    // least-loaded queue; then each queue's tasks in pass-major order.
-    std::vector<size_t> order(ni);
-    for (size_t i = 0; i < ni; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    for (int c = 0; c < kClasses; ++c) {
-        std::vector<double> load(kPersistQueues, 0.0);
-        std::vector<std::vector<size_t>> members(kPersistQueues);
-        for (size_t i : order) {
-            if (b->full[i] == 0 || b->inst[i].p.kind != c) continue;
-            const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            load[q] += cost[i];
-            members[q].push_back(i);
-        }
-        pl->qoff[c].assign(kPersistQueues + 1, 0);
-        pl->qn[c].assign(kPersistQueues, 0);
-        for (int q = 0; q < kPersistQueues; ++q) {
-            pl->qoff[c][q] = (int)pl->tasks.size();
-            // Passes in order of the progress they complete, (p + 1) /
-            // full: every instance advances at the same relative pace, so
-            // instances with many passes are not left alone at the end of
-            // the queue as chains of small passes that cannot fill the XCC.
-            struct Key {
-                double prog;
-                size_t i;
-                int64_t p;
-            };
-            std::vector<Key> keys;
-            for (size_t i : members[q])
-                for (int64_t p = 0; p < b->full[i]; ++p) keys.push_back(Key{(double)(p + 1) / (double)b->full[i], i, p});
-            std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) { return x.prog < y.prog; });
-            int64_t first = 0;
-            for (const Key& k : keys) {
-                pl->tasks.push_back(PersistTask{(int)k.i, (int)((b->par0[k.i] + k.p) & 1), (int)k.p, (int)first});
-                first += items[k.i];
-            }
-            if (first >= (int64_t(1) << 31))
-                return fail(WAVE2D_EINVAL, "batch too large for one persistent launch (%lld items on one XCC)",
-                            (long long)first);
-            pl->qn[c][q] = (int)first;
-        }
-        pl->qoff[c][kPersistQueues] = (int)pl->tasks.size();
-    }
-    return check_plan(b, *pl, items);
+    return persist_plan(in, cap, pl);
 }
 
 // timing: record the batch's events around the persistent launches (not

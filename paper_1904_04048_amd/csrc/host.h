@@ -80,6 +80,48 @@ size_t work_bytes_of(int precision, const Grid& g);
 int run_steps_f32c(const Params& p, uint32_t flags, int64_t steps, float* u, float* lo, float* d, void* work,
                    size_t work_bytes, hipStream_t s);
 
+// ---- persistent launches (persist_plan.hip) -----------------------------------
+// Stencil classes with a persistent kernel (KIND5, KIND9, KIND13).
+constexpr int kPersistClasses = 3;
+// Tallest segment of a persistent work item by default (taller grids are
+// cut into equal segments of at most this many rows).
+constexpr int kPersistRowsCap = 160;
+// Whether the workgroups of a launch land on exactly the kPersistQueues
+// XCCs 0..kPersistQueues-1 (one probe per device): the persistent kernel
+// keys its queues on them.
+bool xcc_layout_ok(int dev);
+// Segment height of an instance's persistent items: the whole grid up to
+// `cap` rows, else the grid cut into equal segments of at most `cap` rows.
+int persist_rows(int ny, int cap);
+// One instance of a persistent launch: its grid, class, weights, the state
+// it starts from (s0) and the other state (s1), its tile counters' offset
+// within its class, its passes and the parity of the first (1: the first
+// pass reads s1).
+struct PersistInput {
+    w2d::Grid g;
+    int kind;
+    w2d::StepW32 w;
+    float* s0[3];
+    float* s1[3];
+    int tile_off;
+    int64_t passes;
+    int par0;
+};
+// Tables of one persistent launch per class: instance records, tasks in
+// per-queue order, queue offsets and item counts.
+struct PersistPlan {
+    std::vector<unsigned char> recs;
+    std::vector<w2d::PersistTask> tasks;     // all classes, class by class
+    std::vector<int> qoff[kPersistClasses];  // per class: task index ranges of the queues (absolute)
+    std::vector<int> qn[kPersistClasses];    // per class: items per queue
+    int64_t items = 0, item_rows = 0;
+};
+// Plan with segments of at most `cap` rows: pin each instance to the
+// least-loaded queue of its class (largest work first) and list each
+// queue's passes in order of the progress they complete.  Checks the
+// plan's invariants before returning.
+int persist_plan(const std::vector<PersistInput>& in, int cap, PersistPlan* pl);
+
 }  // namespace w2d_host
 
 #define W2D_HIP(call)                                                 \
