@@ -821,9 +821,11 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_batch(const
 // id of the XCC it runs on, takes the next item of that XCC's queue (an
 // atomic counter) and, before running it, waits until the tiles whose
 // output it reads have finished the previous pass: the item's own tile
-// (strip x segment) and its neighbours, one strip to each side and `kr`
-// segments up and down (enough for the rows and columns a pass reads
-// beyond its outputs; wrapped on periodic grids).  Each tile keeps a counter
+// (strip x segment) and its neighbours, `ks` strips to each side and `kr`
+// segments up and down (the host finds the reach from the rows and
+// columns each item loads, reflected or wrapped by the boundary rule; on
+// a periodic grid a short last strip or segment can put the wrapped halo
+// two tiles away).  Each tile keeps a counter
 // of its finished passes.  The same wait orders the writes of the next pass
 // after the reads of the previous one: a tile's pass p+1 overwrites the
 // state that the neighbours' pass p read.  Items are taken in queue order,
@@ -861,7 +863,7 @@ struct PInst {
     StepW32 w;
     int kind, nb, items;
     int tile_off;  // first tile counter of the instance (after kPersistTileBase)
-    int kr;        // neighbour segments to wait for on each side
+    int ks, kr;    // neighbour strips / segments to wait for on each side
 };
 
 // Strip and segment of work item `wid` of a pass (boundary items first).
@@ -930,21 +932,32 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
         if (ok) item_tile(dc, pi.nb, wid, strip, seg);
         int* tiles = ctr + kPersistTileBase + pi.tile_off;
         if (t.pass > 0) {
-            // Lane l watches neighbour (strip + l % 3 - 1, seg + l / 3 - kr);
-            // lanes past the neighbourhood, and neighbours off a Dirichlet
-            // grid, watch the item's own tile.
+            // Neighbour n = (strip + n % (2 ks + 1) - ks, seg + n / (2 ks + 1)
+            // - kr), 64 at a time, one per lane; lanes past the last
+            // neighbour, and neighbours off a Dirichlet grid, watch the
+            // item's own tile.
             const int lane = (int)(threadIdx.x & (kWave - 1));
-            const int kr = pi.kr, nst = dc.nstrips, nsg = dc.nseg;
-            int sn = strip + lane % 3 - 1, gn = seg + lane / 3 - kr;
-            bool use = lane < 3 * (2 * kr + 1);
-            if (pi.a[0].g.periodic) {
-                sn = ((sn % nst) + nst) % nst;
-                gn = ((gn % nsg) + nsg) % nsg;
-            } else {
-                use = use && sn >= 0 && sn < nst && gn >= 0 && gn < nsg;
-            }
-            const int* watch = tiles + (use ? gn * nst + sn : seg * nst + strip);
-            if (!__all(__hip_atomic_load(watch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= t.pass)) {
+            const int ks = pi.ks, kr = pi.kr, nst = dc.nstrips, nsg = dc.nseg;
+            const int wsx = 2 * ks + 1, nn = wsx * (2 * kr + 1);
+            const bool per = pi.a[0].g.periodic != 0;
+            auto ready = [&]() {
+                bool all = true;
+                for (int n0 = 0; n0 < nn; n0 += kWave) {
+                    const int n = n0 + lane;
+                    int sn = strip + n % wsx - ks, gn = seg + n / wsx - kr;
+                    bool use = n < nn;
+                    if (per) {
+                        sn = ((sn % nst) + nst) % nst;
+                        gn = ((gn % nsg) + nsg) % nsg;
+                    } else {
+                        use = use && sn >= 0 && sn < nst && gn >= 0 && gn < nsg;
+                    }
+                    const int* watch = tiles + (use ? gn * nst + sn : seg * nst + strip);
+                    all = __all(__hip_atomic_load(watch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= t.pass) && all;
+                }
+                return all;
+            };
+            if (!ready()) {
                 // Poll with a growing pause (up to 64 x 512 cycles); give up
                 // after wait_ticks of the 100 MHz real-time clock, or at once
                 // when another wait of this launch has given up.
@@ -953,7 +966,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 2) void k_stream_persist(con
                 for (int polls = 1;; ++polls) {
                     for (int z = 0; z < pause; ++z) __builtin_amdgcn_s_sleep(8);
                     pause = min(2 * pause, 64);
-                    if (__all(__hip_atomic_load(watch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= t.pass)) break;
+                    if (ready()) break;
                     if ((polls & 7) == 0 && wave_load(stalls) > 0) {
                         ok = false;
                         break;
@@ -1342,11 +1355,35 @@ int persist_inst_k(const Grid& g, const StepW32& w, int rows, int tile_off, floa
     rows = fit_rows<R, DEPTH>(g, rows, sizeof(float));
     const Decomp dc = make_decomp<R, DEPTH, 2>(g, rows);
     if (dc.nstrips * dc.nseg > persist_max_tiles_k<K, DEPTH>(g)) return -1;
-    // An item reads rows y0 - H - NS .. y1 + H + 2 NS of its input: the
-    // segments within 1 + (H + 2 NS) / rows of its own on either side.  Its
-    // columns reach HP < SW beyond its strip: one strip on either side.
-    p.kr = 1 + (H + 2 * NS) / rows;
-    if (3 * (2 * p.kr + 1) > kWave) return -1;
+    // Reach of an item's reads in tiles: the rows it loads (at most
+    // y0 - H - NS .. y1 + H + NS + 1; a margin of NS more each way) and the
+    // columns x0 .. x0 + 127 of its strip, each mapped into the grid by the
+    // boundary rule, and the farthest strip and segment they fall in
+    // (cyclic distance on periodic grids).
+    constexpr int HP = halo_cols<R, DEPTH>();
+    constexpr int SW = kWave * 2 - 2 * HP;
+    const bool per = g.periodic != 0;
+    auto into = [&](int x, int n) {
+        if (per) return ((x % n) + n) % n;
+        const int P = 2 * (n - 1);
+        int m = ((x % P) + P) % P;
+        return m > n - 1 ? P - m : m;
+    };
+    auto dist = [&](int a, int b, int n) {
+        const int d = a > b ? a - b : b - a;
+        return per ? std::min(d, n - d) : d;
+    };
+    int kr = 0, ks = 0;
+    for (int s = 0; s < dc.nseg; ++s) {
+        const int y0 = s * rows, y1 = std::min(y0 + rows, g.ny);
+        for (int y = y0 - H - 2 * NS; y <= y1 - 1 + H + 2 * NS; ++y) kr = std::max(kr, dist(into(y, g.ny) / rows, s, dc.nseg));
+    }
+    for (int s = 0; s < dc.nstrips; ++s) {
+        const int x0 = s * SW - HP;
+        for (int x = x0; x < x0 + kWave * 2; ++x) ks = std::max(ks, dist(into(x, g.nx) / SW, s, dc.nstrips));
+    }
+    p.kr = kr;
+    p.ks = ks;
     p.tile_off = tile_off;
     for (int par = 0; par < 2; ++par) {
         SArgs<float>& a = p.a[par];

@@ -265,3 +265,46 @@ def test_persistent_batch_autotune_keeps_results():
                 assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (c, k)
     finally:
         w.wave2d_batch_destroy(b)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_persistent_batch_random_mixes(seed):
+    # Random mixes of sizes (including grids narrower than one strip and
+    # taller than several segments), schemes, periodic instances, step
+    # counts and segment heights: the persistent plan must equal the rounds
+    # plan bit for bit, with no stalled waits.
+    rng = np.random.default_rng(seed)
+    cases = []
+    for k in range(14):
+        nx = int(rng.integers(8, 700)) & ~1 if k % 3 == 0 else int(rng.integers(5, 700))
+        ny = int(rng.integers(5, 900))
+        scheme = (w.P5, w.P9, w.P13, w.C9)[int(rng.integers(0, 4))]
+        steps = int(rng.integers(1, 120))
+        cases.append((nx, ny, scheme, steps, w.FIRST_CONVENTIONAL if scheme == w.C9 else 0,
+                      float(rng.uniform(0.3, 0.95))))
+    insts = _make(cases, seed=100 + seed)
+    # every third instance of even width runs on the periodic rule
+    for k, t in enumerate(insts):
+        if k % 3 == 0 and t["nx"] % 2 == 0 and t["nx"] >= 5 and t["ny"] >= 5:
+            t["flags"] |= w.PERIODIC
+    br = w.wave2d_batch_create(insts, w.BATCH_ROUNDS)
+    try:
+        _clear(insts)
+        w.wave2d_batch_run(br)
+        torch.cuda.synchronize()
+        refs = [(t["u"].clone(), t["lo"].clone(), t["d"].clone()) for t in insts]
+    finally:
+        w.wave2d_batch_destroy(br)
+    bp = w.wave2d_batch_create(insts)
+    try:
+        for cap in (int(rng.integers(8, 64)), 160, 777):
+            w.wave2d_batch_set_rows_cap(bp, cap)
+            _clear(insts)
+            print(f"random mix seed {seed} rows cap {cap}", flush=True)
+            w.wave2d_batch_run(bp)
+            torch.cuda.synchronize()
+            assert w.wave2d_batch_stats_get(bp)["stalled_waits"] == 0
+            for k, (t, (u, lo, d)) in enumerate(zip(insts, refs)):
+                assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (cap, k)
+    finally:
+        w.wave2d_batch_destroy(bp)
