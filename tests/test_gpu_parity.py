@@ -143,6 +143,48 @@ def test_stream_f32c_bitwise_equals_simple(scheme, depth, rows):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_stream_bitwise_random_shapes(seed):
+    # Random grids (odd and even widths, both boundary rules, padded rows),
+    # schemes, depths, segment heights and step counts: the temporally
+    # blocked kernels equal the one-node-per-thread kernels bit for bit in
+    # both precisions.
+    rng = np.random.default_rng(1000 + seed)
+    for case in range(6):
+        scheme = (w.P5, w.P9, w.P13, w.C9)[int(rng.integers(0, 4))]
+        periodic = bool(rng.integers(0, 2))
+        nx = int(rng.integers(5, 400))
+        ny = int(rng.integers(5, 400))
+        if periodic:
+            nx += nx % 2  # the blocked kernels take even periodic widths
+        ld = nx + int(rng.integers(0, 3)) * 8
+        depth = DEPTHS[int(rng.integers(0, len(DEPTHS)))]
+        rows = int(rng.integers(8, 120))
+        steps = int(rng.integers(1, 3 * depth + 4))
+        fl = (w.PERIODIC if periodic else 0) | (w.FIRST_CONVENTIONAL if scheme == w.C9 else 0)
+        print(f"random shape seed {seed} case {case}: {nx}x{ny} ld {ld} scheme {scheme} periodic {periodic} "
+              f"depth {depth} rows {rows} steps {steps}", flush=True)
+        u0, v0 = rough_data(nx, ny, seed * 100 + case)
+        h = 1.0 / (max(nx, ny) - 1)
+        tau = _lam(scheme, float(rng.uniform(0.3, 1.0))) * h
+        U0, V0 = dev_grid(u0, ld), dev_grid(v0, ld)
+        outs = []
+        for simple in (True, False):
+            if not simple:
+                w.wave2d_set_tuning(w.F64, scheme, depth, rows)
+                w.wave2d_set_tuning(w.F32C, scheme, depth, rows)
+            f = fl | (w.KERNEL_SIMPLE if simple else 0)
+            UP, UC = empty_like_grid(U0), empty_like_grid(U0)
+            w.wave2d_run(U0, V0, UP, UC, h, tau, 1.0, scheme, steps, f)
+            u = empty_like_grid(U0, torch.float32)
+            lo, d = empty_like_grid(U0, torch.float32), empty_like_grid(U0, torch.float32)
+            w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, scheme, steps, f)
+            outs.append([x.clone() for x in (UP, UC, u, lo, d)])
+            assert all(padding_intact(x) for x in (UP, UC, u, lo, d))
+        for a, b in zip(outs[0], outs[1]):
+            assert torch.equal(a, b), case
+
+
 NARROW = [(3, 3), (4, 5), (5, 40), (40, 5), (9, 130), (130, 9), (127, 3), (3, 127), (129, 131)]
 
 
