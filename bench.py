@@ -34,11 +34,11 @@ if ROOT not in sys.path:
 
 METRIC = "grid-point updates/s (GLUP/s) + % HBM roofline; served p50/p99 latency at fixed error"
 HBM_PEAK_GBS = 8000.0
-# Vector ALU issue available to this build: 256 CUs x 4 SIMDs x one wave64
+# Vector ALU issue available to these kernels: 256 CUs x 4 SIMDs x one wave64
 # instruction per 4 cycles (16 lanes per cycle) x 2.4 GHz = 39.3e12 lane
 # operations/s (78.6 TFLOP/s counting a fused multiply-add as two).  The
 # published 157.3 TFLOP/s FP32 figure needs packed FP32 instructions, which
-# this build does not emit.
+# the library is compiled not to emit.
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 STATE_BYTES_PER_NODE = 24  # compensated state (u, lo, d): 12 B read + 12 B written per node per pass
 PROFILES = os.path.join(ROOT, "profiles")
@@ -882,7 +882,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(multi-GPU decomposition is a design note, not part of this build)", file=sys.stderr)
+              "(the library runs on one GPU; a multi-GPU decomposition is described but not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     dev = torch.device("cuda:0")

@@ -4,7 +4,7 @@ Workload of eq. 'exact sol' / 'Exact IC': u0 = 0, v0 = 2 sqrt2 pi sin 2 pi x
 sin 2 pi y on [0,1]^2, c = 1, h = 1/n, tau = lambda h with lambda the literal
 printed value; E(n, n_t) as in eq. error.
 
-Readings (listed in DESIGN.md):
+Readings of the paper these checks rest on:
   * Table 1 rows with n_t = 1 and the whole E_C5 column agree to the printed
     digits; the E_P5 rows with n_t >= n differ from the oracle by up to 0.2 %
     for a reason the paper does not let us recover, so they carry a 2.5e-3
