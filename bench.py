@@ -424,9 +424,10 @@ def off_table_bench(dev):
 def wide_bench(dev):
     """A built scheme reaching three lines out (the complete degree-6 set of
     Sec. 4-5, 25 nodes), 4097^2, 200 levels at 0.9 of its stability limit,
-    FP64 and compensated FP32: one level per launch through LDS-staged
-    tiles, 24 algorithmic bytes per update in both precisions (FP64: u^k and
-    u^{k-1} read, u^{k+1} written; compensated: u, lo, d read and written)."""
+    FP64 and compensated FP32: one level per launch (FP64 through LDS-staged
+    tiles, compensated by waves streaming down column strips), 24
+    algorithmic bytes per update in both precisions (FP64: u^k and u^{k-1}
+    read, u^{k+1} written; compensated: u, lo, d read and written)."""
     import torch
 
     import oracle

@@ -27,7 +27,8 @@ struct WideFirstW {
     int poisson;  // 0: conventional first step (no v0 stencil term)
 };
 
-// One level per launch, LDS-staged tiles (wide.hip).
+// One level per launch (wide.hip): LDS-staged tiles for the first step and
+// FP64, waves streaming down column strips for the compensated update.
 hipError_t wide_first_step(const Grid& g, const WideFirstW& w, const double* u0, const double* v0, double* u1,
                            hipStream_t s);
 hipError_t wide_first_step_f32c(const Grid& g, const WideFirstW& w, const double* u0, const double* v0, float* u,

@@ -2,16 +2,27 @@
 // centre: the schemes that the construction of Sec. 4-5 builds from larger
 // monomial sets (the complete set of degree 6 weights the classes (2,1) and
 // (3,0) besides the 13-point ones).  One level per launch: a block of 64 x 8
-// threads stages its 64 x 32 tile of the level, with a halo of three nodes
-// on every side, in LDS (the boundary rule applied while loading, plain
-// loads for tiles inside the grid), and each thread then forms the class
-// sums of four nodes of one column from LDS.
+// threads stages its tile of the level, with a halo of three nodes on every
+// side, in LDS (the boundary rule applied while loading, plain loads for
+// tiles inside the grid), and each thread forms the class sums of four
+// nodes of one column from LDS.  The FP64 update so moves about as many
+// bytes per second as a device copy.  The compensated update, which does
+// about twice the arithmetic per node, streams instead: each wave walks
+// down a strip of 64 columns, loading rows three ahead of their use, and
+// keeps the 7 x 7 neighbourhood of both fields of its node in registers (a
+// ring of rows; each new row passes through a wave-private LDS row so that
+// every lane picks up its seven columns).  No block barrier, no tile
+// reloads.
 //
 // Node classes (q1, q2), q1 >= q2 >= 0, in this order: (1,0), (1,1), (2,0),
 // (2,1), (2,2), (3,0), (3,1), (3,2), (3,3).  A class holds the rotations of
 // (q1, q2) and, when q1 != q2 and q2 != 0, those of (q2, q1) as well; its
 // sum is taken over (node - centre), opposite nodes paired first, the same
 // way the 5/9/13-point kernels form their rotation sums.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "wide.h"
 
 namespace w2d {
@@ -20,6 +31,7 @@ namespace {
 constexpr int WX = 64, WY = 8, RPT = 4, HALO = 3;  // threads x, y; rows per thread
 constexpr int BH = WY * RPT;                        // rows per block
 constexpr int TX = WX + 2 * HALO, TY = BH + 2 * HALO;
+constexpr int NR = 2 * HALO + 1;                    // rows and columns of a node's neighbourhood
 constexpr int kQ[kWideClasses][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}, {3, 0}, {3, 1}, {3, 2}, {3, 3}};
 
 // Value of node (i, j) under the boundary rule, for (i, j) up to three
@@ -91,6 +103,21 @@ __device__ __forceinline__ T class_sum(const T (*t)[TX], int ly, int lx)
     return s;
 }
 
+// The same sum from a thread's register neighbourhood: w[(cs + dy) mod NR]
+// [HALO + dx] holds the node at offset (dx, dy) from the centre, cs being
+// the centre row's slot (a compile-time constant once the row loop is
+// unrolled).  Same operands in the same order as class_sum.
+template <typename T, int C>
+__device__ __forceinline__ T class_sum_w(const T (&w)[NR][NR], int cs)
+{
+    constexpr int q1 = kQ[C][0], q2 = kQ[C][1];
+    auto at = [&](int dy, int dx) { return w[(cs + dy + NR) % NR][HALO + dx]; };
+    const T c = at(0, 0);
+    T s = ((at(q2, q1) - c) + (at(-q2, -q1) - c)) + ((at(q1, -q2) - c) + (at(-q1, q2) - c));
+    if constexpr (q2 != 0 && q2 != q1) s = s + (((at(q1, q2) - c) + (at(-q1, -q2) - c)) + ((at(q2, -q1) - c) + (at(-q2, q1) - c)));
+    return s;
+}
+
 // sum_c w[c] S_c in class order, skipping classes without weight.
 template <int C = 0>
 __device__ __forceinline__ double wide_sum(const double (*t)[TX], int ly, int lx, const double* w, double s)
@@ -113,6 +140,18 @@ __device__ __forceinline__ float wide_sum_f32c(const float (*tu)[TX], const floa
     if constexpr (C < kWideClasses) {
         if (w[C] != 0.f) s = s + mul_w2(w[C], wl[C], class_sum<float, C>(tu, ly, lx) + class_sum<float, C>(tl, ly, lx));
         return wide_sum_f32c<C + 1>(tu, tl, ly, lx, w, wl, s);
+    } else {
+        return s;
+    }
+}
+
+template <int C = 0>
+__device__ __forceinline__ float wide_sum_f32c_w(const float (&wu)[NR][NR], const float (&wl)[NR][NR], int cs,
+                                                 const float* w, const float* wlo, float s)
+{
+    if constexpr (C < kWideClasses) {
+        if (w[C] != 0.f) s = s + mul_w2(w[C], wlo[C], class_sum_w<float, C>(wu, cs) + class_sum_w<float, C>(wl, cs));
+        return wide_sum_f32c_w<C + 1>(wu, wl, cs, w, wlo, s);
     } else {
         return s;
     }
@@ -192,38 +231,198 @@ __global__ __launch_bounds__(WX* WY) void k_wide_step_f64(Grid g, WideW64 w, con
     }
 }
 
-// Compensated FP32 two-step update: (u, lo, d) -> (u2, lo2, d2).
-__global__ __launch_bounds__(WX* WY) void k_wide_step_f32c(Grid g, WideW32 w, const float* __restrict__ u,
-                                                           const float* __restrict__ lo,
-                                                           const float* __restrict__ d, float* __restrict__ u2,
-                                                           float* __restrict__ lo2, float* __restrict__ d2)
+// Compensated FP32 two-step update: (u, lo, d) -> (u2, lo2, d2), by waves
+// streaming down strips (see the top of the file).
+constexpr int SWW = 64;            // output columns per wave, one per lane
+constexpr int PFW = 2;             // rows loaded ahead of their first use
+constexpr int kWideWaves = 4;      // waves per block (independent: no barrier)
+constexpr int kWideRounds = 4;     // work items per resident wave the segment height aims at
+
+// Grid node that node x of the extended line stands for (idx) and the
+// factor its value is read with: the rule of wide_load, 1 or -1 (mirror
+// image), or 0 (a boundary line, or a mirror beyond it; idx is then 0).
+__device__ __forceinline__ int wide_map(int x, int n, bool periodic, int& idx)
 {
-    __shared__ float tu[TY][TX], tl[TY][TX];
-    const int x0 = blockIdx.x * WX, y0 = blockIdx.y * BH;
-    load_tile(tu, u, g, x0, y0);
-    load_tile(tl, lo, g, x0, y0);
-    __syncthreads();
-    const int i = x0 + threadIdx.x;
-    if (i >= g.nx) return;
-    const int lx = threadIdx.x + HALO;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int ry = threadIdx.y * RPT + k, j = y0 + ry;
-        if (j >= g.ny) break;
-        const size_t o = (size_t)j * g.ld + i;
-        float ru = 0.f, rl = 0.f, rd = 0.f;
-        if (wide_interior(g, i, j)) {
-            const int ly = ry + HALO;
-            const float s = wide_sum_f32c(tu, tl, ly, lx, w.w, w.wl, 0.f);
-            f32c_update(s, tu[ly][lx], tl[ly][lx], d[o], ru, rl, rd);
+    if (periodic) {
+        int m = x % n;
+        m += (m < 0) ? n : 0;
+        idx = m;
+        return 1;
+    }
+    int sg = 1;
+    if (x < 0) {
+        x = -x;
+        sg = -sg;
+    } else if (x > n - 1) {
+        x = 2 * (n - 1) - x;
+        sg = -sg;
+    }
+    if (x <= 0 || x >= n - 1) {
+        idx = 0;
+        return 0;
+    }
+    idx = x;
+    return sg;
+}
+
+// Ordering of a wave's LDS accesses across its lanes: the wave's LDS
+// operations execute in program order, so only the compiler must keep
+// them in order (a lane's read of another lane's write is invisible to
+// its per-thread analysis).
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(SWW* kWideWaves) void k_wide_step_f32c(Grid g, WideW32 w, const float* __restrict__ u,
+                                                                     const float* __restrict__ lo,
+                                                                     const float* __restrict__ d,
+                                                                     float* __restrict__ u2, float* __restrict__ lo2,
+                                                                     float* __restrict__ d2, int segw)
+{
+    __shared__ float rowbuf[kWideWaves][2][SWW + 2 * HALO];
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int nx = g.nx, ny = g.ny;
+    const int nstrips = (nx + SWW - 1) / SWW, nseg = (ny + segw - 1) / segw;
+    const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWideWaves + wave);
+    if (item >= nstrips * nseg) return;  // whole waves; no barrier follows
+    const int x0 = (item % nstrips) * SWW, y0 = (item / nstrips) * segw, y1 = min(y0 + segw, ny);
+    const bool per = g.periodic != 0;
+    // The lane's output column xm; lanes 0..5 also load one halo column
+    // (three on each side).  LDS slot s of a row holds column x0 - 3 + s.
+    const int xm = x0 + lane;
+    const bool has_h = lane < 2 * HALO;
+    const int xh = (lane < HALO) ? x0 - HALO + lane : x0 + SWW + lane - HALO;
+    int im = 0, ih = 0;
+    const int sm = wide_map(xm, nx, per, im);
+    const int sh = has_h ? wide_map(xh, nx, per, ih) : 0;
+    const int slot_m = HALO + lane, slot_h = (lane < HALO) ? lane : SWW + lane;
+    // Columns read as stored for every lane (no sign or zero to apply).
+    const int lb = per ? 0 : 1;
+    const bool plain_cols = x0 - HALO >= lb && x0 + SWW - 1 + HALO <= nx - 1 - lb;
+    float* const bu = rowbuf[wave][0];
+    float* const bl = rowbuf[wave][1];
+
+    // Row r of the extended grid, both fields, main and halo column.
+    auto load_row = [&](int r, float (&v)[2][2]) {
+        int jr;
+        const int sr = wide_map(r, ny, per, jr);
+        const size_t ro = (size_t)jr * g.ld;
+        const float a0 = u[ro + im], a1 = lo[ro + im];
+        float b0 = 0.f, b1 = 0.f;
+        if (has_h) {
+            b0 = u[ro + ih];
+            b1 = lo[ro + ih];
         }
-        u2[o] = ru;
-        lo2[o] = rl;
-        d2[o] = rd;
+        if (plain_cols && sr == 1) {
+            v[0][0] = a0;
+            v[1][0] = a1;
+            v[0][1] = b0;
+            v[1][1] = b1;
+        } else {
+            const float fm = (float)(sr * sm), fh = (float)(sr * sh);
+            v[0][0] = (fm != 0.f) ? a0 * fm : 0.f;
+            v[1][0] = (fm != 0.f) ? a1 * fm : 0.f;
+            v[0][1] = (fh != 0.f) ? b0 * fh : 0.f;
+            v[1][1] = (fh != 0.f) ? b1 * fh : 0.f;
+        }
+    };
+    // d at output row j (clamped into the grid: rows and columns without an
+    // output are loaded but never used).
+    const int xd = min(xm, nx - 1);
+    auto load_d = [&](int j) { return d[(size_t)min(j, ny - 1) * g.ld + xd]; };
+
+    float W[2][NR][NR];   // [field][row slot][column]: row y0 + k sits in slot k mod 7
+    float st[NR][2][2];   // loaded rows on their way to the window, by the same slot
+    float dr[NR];         // d of output rows, by slot
+    auto enter = [&](const float (&v)[2][2], int slot) {
+        wave_lds_order();
+        bu[slot_m] = v[0][0];
+        bl[slot_m] = v[1][0];
+        if (has_h) {
+            bu[slot_h] = v[0][1];
+            bl[slot_h] = v[1][1];
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            W[0][slot][c] = bu[lane + c];
+            W[1][slot][c] = bl[lane + c];
+        }
+    };
+#pragma unroll
+    for (int r = -HALO; r < HALO; ++r) {
+        float v[2][2];
+        load_row(y0 + r, v);
+        enter(v, (r + NR) % NR);
+    }
+#pragma unroll
+    for (int r = 0; r < PFW; ++r) {
+        load_row(y0 + HALO + r, st[(HALO + r) % NR]);
+        dr[r % NR] = load_d(y0 + r);
+    }
+    for (int k0 = 0; y0 + k0 < y1; k0 += NR) {
+#pragma unroll
+        for (int kk = 0; kk < NR; ++kk) {
+            const int j = y0 + k0 + kk;
+            enter(st[(kk + HALO) % NR], (kk + HALO) % NR);
+            load_row(j + HALO + PFW, st[(kk + HALO + PFW) % NR]);
+            dr[(kk + PFW) % NR] = load_d(j + PFW);
+            if (j < y1 && xm < nx) {
+                const size_t o = (size_t)j * g.ld + xm;
+                float ru = 0.f, rl = 0.f, rd = 0.f;
+                if (wide_interior(g, xm, j)) {
+                    const float s = wide_sum_f32c_w(W[0], W[1], kk, w.w, w.wl, 0.f);
+                    f32c_update(s, W[0][kk][HALO], W[1][kk][HALO], dr[kk], ru, rl, rd);
+                }
+                u2[o] = ru;
+                lo2[o] = rl;
+                d2[o] = rd;
+            }
+        }
     }
 }
 
 dim3 wide_grid(const Grid& g) { return dim3((g.nx + WX - 1) / WX, (g.ny + BH - 1) / BH); }
+
+// Output rows per wave of the compensated update: a multiple of 7 (whole
+// turns of the register ring), the largest that still gives about
+// kWideRounds work items per resident wave (shorter segments reload more
+// rows above and below, taller ones leave waves idle on small grids).
+int wide_stream_rows(const Grid& g)
+{
+    static std::mutex mu;
+    static std::map<int, int> slots;  // resident waves per device
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int res;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = slots.find(dev);
+        if (it == slots.end()) {
+            int nb = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_wide_step_f32c),
+                                                             SWW * kWideWaves, 0) != hipSuccess || nb < 1)
+                nb = 1;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            (void)hipGetLastError();
+            it = slots.emplace(dev, nb * kWideWaves * cus).first;
+        }
+        res = it->second;
+    }
+    const long long groups = (long long)((g.nx + SWW - 1) / SWW) * ((g.ny + NR - 1) / NR);
+    const long long m = groups / ((long long)kWideRounds * res);
+    return NR * (int)std::max(1LL, std::min(16LL, m));
+}
+
+int wide_stream_blocks(const Grid& g, int segw)
+{
+    const int items = ((g.nx + SWW - 1) / SWW) * ((g.ny + segw - 1) / segw);
+    return (items + kWideWaves - 1) / kWideWaves;
+}
 
 }  // namespace
 
@@ -251,7 +450,8 @@ hipError_t wide_step_f64(const Grid& g, const WideW64& w, const double* u_prev, 
 hipError_t wide_step_f32c(const Grid& g, const WideW32& w, const float* u, const float* lo, const float* d,
                           float* u2, float* lo2, float* d2, hipStream_t s)
 {
-    k_wide_step_f32c<<<wide_grid(g), dim3(WX, WY), 0, s>>>(g, w, u, lo, d, u2, lo2, d2);
+    const int segw = wide_stream_rows(g);
+    k_wide_step_f32c<<<wide_stream_blocks(g, segw), SWW * kWideWaves, 0, s>>>(g, w, u, lo, d, u2, lo2, d2, segw);
     return hipGetLastError();
 }
 
