@@ -47,6 +47,7 @@ BATCH_COUNTERS = os.path.join(PROFILES, "k_stream_persist_batch512_counters.md")
 BATCH_STATS = os.path.join(PROFILES, "k_stream_persist_batch512_kernel_stats.md")
 C2_COUNTERS = os.path.join(PROFILES, "k_stream_fused_f32c_9pt_4097_counters.md")
 C3_COUNTERS = os.path.join(PROFILES, "k_stream_fused_f32c_13pt_8193_counters.md")
+WIDE_COUNTERS = os.path.join(PROFILES, "k_wide_step_f32c_deg6_4097_counters.md")
 
 
 def parse():
@@ -77,6 +78,15 @@ def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     for f in ("stream.hip", "point.h", "w2d.h"):
+        h.update(open(os.path.join(ROOT, "paper_1904_04048_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def wide_source_hash():
+    """Hash of the sources the wide-scheme kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("wide.hip", "wide.h", "point.h", "w2d.h"):
         h.update(open(os.path.join(ROOT, "paper_1904_04048_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -434,7 +444,7 @@ def wide_bench(dev):
     import paper_1904_04048_amd as w
     from oracle import derive
     from paper_1904_04048_amd import workloads as W
-    sid = w.wave2d_scheme_create(derive.stencil(28), derive.monomials(28))
+    sid = w.wave2d_scheme_create(*W.complete_set(6))
     n, steps = 4097, 200
     h = 1.0 / (n - 1)
     tau = 0.9 * w.wave2d_lambda_max(sid) * h
@@ -477,11 +487,12 @@ def wide_bench(dev):
     Ps, Cs = torch.empty_like(U0s), torch.empty_like(U0s)
     w.wave2d_run(U0s, V0s, Ps, Cs, hs, taus, 1.0, sid, 400)
     alg = STATE_BYTES_PER_NODE * n * n
+    cfg = {"kernel": "k_wide_step_f32c", "grid": [n, n], "source": wide_source_hash()}
     return {"workload": "built scheme, complete degree-6 set (25 nodes, radius 3), 4097x4097, 200 levels",
             "value": round(lup / t32 / 1e9, 2), "unit": "GLUP/s", "ms_per_solve": round(t32 * 1e3, 2),
             "fp64_value": round(lup / t64 / 1e9, 2), "fp64_ms_per_solve": round(t64 * 1e3, 2),
-            "roofline": roofline_hbm(alg, t_level, (n - 2) * (n - 2), None,
-                                     "k_wide_step_f32c (one level per launch)", {}),
+            "roofline": roofline_hbm(alg, t_level, (n - 2) * (n - 2), traffic_record(WIDE_COUNTERS, cfg),
+                                     "k_wide_step_f32c (one level per launch)", {"alu": alu_view(WIDE_COUNTERS)}),
             "error": {"max_rel_f32c_vs_gpu_fp64": f32_vs_f64,
                       "copy_257_400_levels": {"max_rel_f32c_vs_oracle": oracle.rel_max_err(outs.cpu().numpy(), ref),
                                               "max_rel_fp64_vs_oracle": oracle.rel_max_err(Cs.cpu().numpy(), ref)}}}
@@ -656,8 +667,9 @@ def cpu_baseline(budget_s=12.0):
 
 def profile_run(dev):
     """Short run for rocprofv3 counter passes: a 256 MiB device copy (the
-    counters' calibration), one run of the batch, and ten passes each of the
-    4097^2 9-point and 8193^2 13-point single-grid kernels."""
+    counters' calibration), one run of the batch, ten passes each of the
+    4097^2 9-point and 8193^2 13-point single-grid kernels, and ten levels of
+    the degree-6 built scheme's compensated kernel at 4097^2."""
     import torch
 
     import paper_1904_04048_amd as w
@@ -693,7 +705,18 @@ def profile_run(dev):
         shapes[str(p.scheme)] = {"depth": depth, "rows": rows, "grid": [p.nx, p.ny]}
         del U0, V0, u, lo, d, work
         torch.cuda.empty_cache()
+    import numpy as np
+    sid = w.wave2d_scheme_create(*W.complete_set(6))
+    n = 4097
+    rng = np.random.default_rng(0)
+    u, lo, d = (torch.from_numpy(rng.uniform(-0.5, 0.5, (n, n)).astype(np.float32) * s).to(dev)
+                for s in (1.0, 1e-8, 1e-3))
+    h = 1.0 / (n - 1)
+    w.wave2d_f32c_step(u, lo, d, h, 0.9 * w.wave2d_lambda_max(sid) * h, 1.0, sid, 10)
+    torch.cuda.synchronize()
+    del u, lo, d
     print(json.dumps({"profile": "done", "rows_cap": cap, "shapes": shapes, "source": kernel_source_hash(),
+                      "wide": {"grid": [n, n], "source": wide_source_hash()},
                       "batch": {"persistent_bytes": st["persistent_bytes"], "persistent_lup": st["persistent_lup"]},
                       "copy_bytes": 2 * 256 * 1024 * 1024}), flush=True)
 
@@ -819,6 +842,12 @@ def summarize(prof_dir):
             {"kernel": f"k_stream_fused<PF32C,{name}>", "depth": sh["depth"], "rows": sh["rows"],
              "grid": [p.nx, p.ny], "source": rec["source"]},
             STATE_BYTES_PER_NODE * p.nx * p.ny, p.interior * sh["depth"])
+    if "wide" in rec:
+        n = rec["wide"]["grid"][0]
+        one(f"HBM traffic and issue of one level of the degree-6 built scheme's compensated kernel, {n} x {n}",
+            WIDE_COUNTERS, lambda k: "k_wide_step_f32c" in k,
+            {"kernel": "k_wide_step_f32c", "grid": [n, n], "source": rec["wide"]["source"]},
+            STATE_BYTES_PER_NODE * n * n, (n - 2) * (n - 2))
 
     tpath = os.path.join(prof_dir, "prof_bench", "bench_kernel_stats.csv")
     if os.path.exists(tpath):

@@ -210,3 +210,23 @@ def poisson_arrivals(count: int, qps: float, seed: int = 1):
     """Arrival times (s) of a Poisson process of rate qps."""
     rng = np.random.Generator(np.random.PCG64(seed + 1000))
     return np.cumsum(rng.exponential(1.0 / qps, size=count))
+
+
+def complete_set(deg: int):
+    """The complete monomial set of degree `deg` and its stencil, as inputs
+    for a scheme built at run time (Sec. 4, eq. alpha and g): exponent pairs
+    (a1, a2) with a1 + a2 <= deg, degree by degree, within a degree in the
+    order of eq. g (a1 = a2 first, then a1 - a2 = 1, -1, 2, -2, ...), and
+    the node (q(a1), q(a2)) of each, q(a) = (-1)^a floor((a + 1) / 2) being
+    the inverse of eq. alpha.  Degree 6 gives the 28 monomials M*_{<=28}
+    and their 28 nodes."""
+    def q(a: int) -> int:
+        return (-1) ** a * ((a + 1) // 2)
+
+    exps: List[Tuple[int, int]] = []
+    for d in range(deg + 1):
+        pairs = [(a1, d - a1) for a1 in range(d + 1)]
+        # position within the degree by eq. g: a1 - a2 for a1 > a2, a2 - a1 + 1 otherwise
+        pairs.sort(key=lambda e: e[0] - e[1] if e[1] < e[0] else e[1] - e[0] + 1)
+        exps += pairs
+    return [(q(a1), q(a2)) for a1, a2 in exps], exps

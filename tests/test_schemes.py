@@ -42,6 +42,17 @@ def cross_oracle():
     return wts
 
 
+@pytest.mark.parametrize("deg,m", [(1, 3), (2, 6), (3, 10), (4, 15), (5, 21), (6, 28)])
+def test_workload_complete_sets_are_the_paper_sets(deg, m):
+    """The input generator's complete monomial sets (used to build schemes
+    in the benchmark) are the paper's M*_{<=m} in the order of eq. g, with
+    the stencil Q_m of eq. invMcKinney."""
+    from paper_1904_04048_amd import workloads as W
+    nodes, exps = W.complete_set(deg)
+    assert exps == derive.monomials(m)
+    assert nodes == derive.stencil(m)
+
+
 def test_oracle_generic_construction_equals_paper_sets():
     for m in (6, 11, 15):
         assert derive.node_weights_for(derive.stencil(m), derive.monomials(m)) == derive.node_weights(m)
