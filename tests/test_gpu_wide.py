@@ -177,3 +177,29 @@ def test_wide_scheme_refused_by_batch_server_and_autotune(deg6):
         w.wave2d_server_destroy(sv)
     with pytest.raises(w.Wave2dError):
         w.wave2d_autotune(w.F32C, deg6, 256, 256)
+
+
+@pytest.mark.parametrize("shape", [(4097, 4097), (8193, 4097)], ids=["4097x4097", "8193x4097"])
+def test_wide_compensated_on_large_grids(deg6, shape):
+    """Grids large enough that the compensated kernel's segment rule picks
+    segments of several turns of its seven-row register ring (on MI355X,
+    14 rows at 4097^2 and 28 at 8193 x 4097), against the oracle after a
+    few levels, with FP64 alongside."""
+    nx, ny = shape
+    (u0, v0), _ = smooth_data(nx, ny, 3)
+    h = 1.0 / (nx - 1)
+    tau = 0.9 * w.wave2d_lambda_max(deg6) * h
+    steps = 5
+    print(f"wide scheme {nx}x{ny}, {steps} levels", flush=True)
+    _, rc = oracle.run(u0, v0, h, tau, 1.0, ORC_DEG6, steps)
+    U0, V0 = dev_grid(u0), dev_grid(v0)
+    del u0, v0
+    u = torch.full(U0.shape, float("nan"), dtype=torch.float32, device=U0.device)
+    lo, d = torch.full_like(u, float("nan")), torch.full_like(u, float("nan"))
+    w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, deg6, steps)
+    out = torch.empty_like(U0)
+    w.wave2d_f32c_export(u, lo, out)
+    assert oracle.rel_max_err(out.cpu().numpy(), rc) <= 1e-5
+    P, C = torch.empty_like(U0), torch.empty_like(U0)
+    w.wave2d_run(U0, V0, P, C, h, tau, 1.0, deg6, steps)
+    assert oracle.rel_max_err(C.cpu().numpy(), rc) <= 1e-12
