@@ -371,27 +371,34 @@ __device__ __forceinline__ void row_update_carry(const double (&Wc)[1][CW], cons
 // Work decomposition shared by the host and both kernels: strips of SW
 // output columns, segments of `rows` output rows, and the rectangle of
 // (strip, segment) pairs whose whole stream stays inside the grid interior
-// (strips [s_lo, s_lo + ns), segments [g_lo, g_lo + ng)).
+// (strips [s_lo, s_lo + ns), segments [g_lo, g_lo + ng)).  The edge strips
+// (outside [s_lo, s_lo + ns)), whose items reflect columns on every row and
+// run longer, may be cut into shorter segments of their own: nseg_e
+// segments of rows_e rows (rows_e = rows in batched and persistent
+// launches).
 struct Decomp {
-    int nstrips, nseg, s_lo, ns, g_lo, ng;
+    int nstrips, nseg, s_lo, ns, g_lo, ng, nseg_e, rows_e;
 };
 
 // Map a boundary work id (the complement of the interior rectangle) to
-// (strip, segment): first every strip of the segments outside the interior
-// range, then the edge strips of the interior segments.
-__device__ __forceinline__ void boundary_item(const Decomp& d, int wid, int& strip, int& seg)
+// (strip, segment) and the item's segment height: first every segment of
+// the edge strips, then the interior strips' segments outside the interior
+// range.
+__device__ __forceinline__ void boundary_item(const Decomp& d, int rows, int wid, int& strip, int& seg, int& h)
 {
-    const int outer = (d.nseg - d.ng) * d.nstrips;
-    if (wid < outer) {
-        const int k = wid / d.nstrips;
-        strip = wid % d.nstrips;
-        seg = (k < d.g_lo) ? k : k + d.ng;
-    } else {
-        const int w2 = wid - outer;
-        const int ne = d.nstrips - d.ns;
-        seg = d.g_lo + w2 / ne;
-        const int k = w2 % ne;
+    const int ne = d.nstrips - d.ns;
+    const int first = ne * d.nseg_e;
+    if (wid < first) {
+        const int k = wid % ne;
         strip = (k < d.s_lo) ? k : k + d.ns;
+        seg = wid / ne;
+        h = d.rows_e;
+    } else {
+        const int w2 = wid - first;
+        strip = d.s_lo + w2 % d.ns;
+        const int k = w2 / d.ns;
+        seg = (k < d.g_lo) ? k : k + d.ng;
+        h = rows;
     }
 }
 
@@ -479,9 +486,9 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     static_assert(CW == 2, "reflected loads assume column pairs");
 
     const int lane = threadIdx.x & (kWave - 1);
-    int strip, seg;
+    int strip, seg, rows = a.rows;
     if constexpr (BND) {
-        boundary_item(dc, wid, strip, seg);
+        boundary_item(dc, a.rows, wid, strip, seg, rows);
     } else {
         strip = dc.s_lo + wid % dc.ns;
         seg = dc.g_lo + wid / dc.ns;
@@ -489,8 +496,8 @@ __device__ __forceinline__ void stream_body(const SArgs<typename Prec::T>& a, co
     const int nx = a.g.nx, ny = a.g.ny, ld = a.g.ld;
     const int x0 = strip * SW - HP;
     const int xl = x0 + lane * CW;
-    const int y0 = seg * a.rows;
-    const int y1 = min(y0 + a.rows, ny);
+    const int y0 = seg * rows;
+    const int y1 = min(y0 + rows, ny);
     const bool st_lane = (xl >= x0 + HP) && (xl < x0 + HP + SW) && (!BND || xl < nx);
     // The last lane of an odd-width grid stores its first column only.
     const bool st_full = !BND || (xl + CW <= nx);
@@ -870,7 +877,8 @@ struct PInst {
 __device__ __forceinline__ void item_tile(const Decomp& dc, int nb, int wid, int& strip, int& seg)
 {
     if (wid < nb) {
-        boundary_item(dc, wid, strip, seg);
+        int h;
+        boundary_item(dc, 0, wid, strip, seg, h);  // one segmentation: h is not needed
     } else {
         const int k = wid - nb;
         strip = dc.s_lo + k % dc.ns;
@@ -1007,7 +1015,7 @@ __global__ void k_xcc_probe(int* out, int n)
 }
 
 template <int R, int DEPTH, int CW>
-Decomp make_decomp(const Grid& g, int rows)
+Decomp make_decomp(const Grid& g, int rows, int rows_e = 0)
 {
     constexpr int NS = 2 * R + 1;
     constexpr int H = R * DEPTH;
@@ -1039,7 +1047,10 @@ Decomp make_decomp(const Grid& g, int rows)
     if (d.ns == 0 || d.ng == 0) {
         d.ns = d.ng = 0;
         d.s_lo = d.g_lo = 0;
+        rows_e = 0;  // every item is a boundary item of one segmentation
     }
+    d.rows_e = (rows_e > 0) ? rows_e : rows;
+    d.nseg_e = (g.ny + d.rows_e - 1) / d.rows_e;
     return d;
 }
 
@@ -1054,6 +1065,42 @@ int fit_rows(const Grid& g, int rows, size_t elt)
     return (int)std::max<long long>(1, std::min<long long>(rows, cap));
 }
 
+// Segment heights of a single-grid pass with `rows` the tuned height: the
+// edge strips' items reflect columns on every row and take about kEdgeCost
+// times as long per row, so their segments are cut shorter, such that
+// rows_e + c0 = (rows + c0) / kEdgeCost with c0 = 2H + NS the rows an item
+// streams beyond its outputs; the interior strips' segments then grow
+// until the pass has no more work items than with `rows` throughout, so
+// that the tuned filling of the device's wave slots holds.  Where no
+// height up to twice `rows` achieves that, or the grid has no interior
+// strips, both stay `rows`.  Heights beyond what fit_rows allows are
+// never taken.
+constexpr double kEdgeCost = 1.16;
+
+template <int R, int DEPTH>
+void edge_rows(const Grid& g, size_t elt, int& rows, int& rows_e)
+{
+    constexpr int c0 = 2 * R * DEPTH + 2 * R + 1;
+    const Decomp d0 = make_decomp<R, DEPTH, 2>(g, rows);
+    rows_e = rows;
+    const int ne = d0.nstrips - d0.ns;
+    if (d0.ns == 0 || ne == 0) return;
+    const int re = (int)((rows + c0) / kEdgeCost) - c0;
+    if (re < kPersistMinRows || re >= rows) return;
+    const long long budget = (long long)d0.nstrips * d0.nseg;
+    const long long edge_items = (long long)ne * ((g.ny + re - 1) / re);
+    for (int ri = rows; ri <= 2 * rows; ++ri) {
+        if (fit_rows<R, DEPTH>(g, ri, elt) != ri) return;
+        if (edge_items + (long long)d0.ns * ((g.ny + ri - 1) / ri) <= budget) {
+            const Decomp d1 = make_decomp<R, DEPTH, 2>(g, ri, re);
+            if (d1.ns != d0.ns) return;
+            rows = ri;
+            rows_e = re;
+            return;
+        }
+    }
+}
+
 template <class Prec, int K, int DEPTH>
 hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, const Fork* fork,
                         SArgs<typename Prec::T> a, hipStream_t s)
@@ -1063,13 +1110,15 @@ hipError_t launch_depth(const Grid& g, const typename Prec::W& w, int rows, cons
     constexpr int SW = kWave * CW - 2 * halo_cols<R, DEPTH>();
     static_assert(SW > 0, "strip too narrow");
     rows = fit_rows<R, DEPTH>(g, rows, sizeof(typename Prec::T));
+    int rows_e = rows;
+    edge_rows<R, DEPTH>(g, sizeof(typename Prec::T), rows, rows_e);
     a.g = g;
     a.rows = rows;
-    const Decomp dc = make_decomp<R, DEPTH, CW>(g, rows);
+    const Decomp dc = make_decomp<R, DEPTH, CW>(g, rows, rows_e);
     a.nstrips = dc.nstrips;
-    a.nwork = dc.nstrips * dc.nseg;
-    const int nb = a.nwork - dc.ns * dc.ng;
     const int ni = dc.ns * dc.ng;
+    const int nb = (dc.nstrips - dc.ns) * dc.nseg_e + dc.ns * (dc.nseg - dc.ng);
+    a.nwork = nb + ni;
     // One launch per pass (measured on 4097^2 9-point compensated: 786 ->
     // 826 GLUP/s against a boundary kernel on a side stream beside the
     // interior kernel; 2049^2: 442 -> 579).
