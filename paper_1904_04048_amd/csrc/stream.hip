@@ -1066,16 +1066,18 @@ int fit_rows(const Grid& g, int rows, size_t elt)
 }
 
 // Segment heights of a single-grid pass with `rows` the tuned height: the
-// edge strips' items reflect columns on every row and take about kEdgeCost
-// times as long per row, so their segments are cut shorter, such that
-// rows_e + c0 = (rows + c0) / kEdgeCost with c0 = 2H + NS the rows an item
-// streams beyond its outputs; the interior strips' segments then grow
+// edge strips' items reflect columns on every row and take longer per row
+// (edge_cost: measured best ratios on MI355X, 1.16 for the 5- and 9-point
+// kernels, 1.36 for the 13-point ones), so their segments are cut shorter,
+// such that rows_e + c0 = (rows + c0) / edge_cost with c0 = 2H + NS the
+// rows an item streams beyond its outputs; the interior strips' segments then grow
 // until the pass has no more work items than with `rows` throughout, so
 // that the tuned filling of the device's wave slots holds.  Where no
 // height up to twice `rows` achieves that, or the grid has no interior
 // strips, both stay `rows`.  Heights beyond what fit_rows allows are
 // never taken.
-constexpr double kEdgeCost = 1.16;
+template <int R>
+constexpr double edge_cost() { return R == 1 ? 1.16 : 1.36; }
 
 template <int R, int DEPTH>
 void edge_rows(const Grid& g, size_t elt, int& rows, int& rows_e)
@@ -1085,7 +1087,7 @@ void edge_rows(const Grid& g, size_t elt, int& rows, int& rows_e)
     rows_e = rows;
     const int ne = d0.nstrips - d0.ns;
     if (d0.ns == 0 || ne == 0) return;
-    const int re = (int)((rows + c0) / kEdgeCost) - c0;
+    const int re = (int)((rows + c0) / edge_cost<R>()) - c0;
     if (re < kPersistMinRows || re >= rows) return;
     const long long budget = (long long)d0.nstrips * d0.nseg;
     const long long edge_items = (long long)ne * ((g.ny + re - 1) / re);
