@@ -381,12 +381,31 @@ struct Decomp {
 };
 
 // Map a boundary work id (the complement of the interior rectangle) to
-// (strip, segment) and the item's segment height: first every segment of
-// the edge strips, then the interior strips' segments outside the interior
+// (strip, segment) and the item's segment height.  One segmentation: first
+// every strip of the segments outside the interior range, then the edge
+// strips of the interior segments (a persistent launch then finishes the
+// rows above the interior first, which the next pass's items there wait
+// for).  Edge strips in segments of their own: first every segment of the
+// edge strips, then the interior strips' segments outside the interior
 // range.
 __device__ __forceinline__ void boundary_item(const Decomp& d, int rows, int wid, int& strip, int& seg, int& h)
 {
     const int ne = d.nstrips - d.ns;
+    h = rows;
+    if (d.rows_e == rows) {
+        const int outer = (d.nseg - d.ng) * d.nstrips;
+        if (wid < outer) {
+            const int k = wid / d.nstrips;
+            strip = wid % d.nstrips;
+            seg = (k < d.g_lo) ? k : k + d.ng;
+        } else {
+            const int w2 = wid - outer;
+            seg = d.g_lo + w2 / ne;
+            const int k = w2 % ne;
+            strip = (k < d.s_lo) ? k : k + d.ns;
+        }
+        return;
+    }
     const int first = ne * d.nseg_e;
     if (wid < first) {
         const int k = wid % ne;
@@ -878,7 +897,7 @@ __device__ __forceinline__ void item_tile(const Decomp& dc, int nb, int wid, int
 {
     if (wid < nb) {
         int h;
-        boundary_item(dc, 0, wid, strip, seg, h);  // one segmentation: h is not needed
+        boundary_item(dc, dc.rows_e, wid, strip, seg, h);  // one segmentation
     } else {
         const int k = wid - nb;
         strip = dc.s_lo + k % dc.ns;
