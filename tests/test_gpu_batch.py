@@ -308,3 +308,33 @@ def test_persistent_batch_random_mixes(seed):
                 assert torch.equal(t["u"], u) and torch.equal(t["lo"], lo) and torch.equal(t["d"], d), (cap, k)
     finally:
         w.wave2d_batch_destroy(bp)
+
+
+def test_full_batch_repeats_bitwise():
+    """The 512-instance batch of the benchmark (persistent launches, all
+    three classes concurrently): ten runs give the first run's bits in every
+    instance, outputs cleared to NaN before each run."""
+    from paper_1904_04048_amd import workloads as W
+    dev = torch.device("cuda:0")
+    insts = []
+    for pr in W.c4():
+        U0, V0 = W.sine_series_torch(pr.nx, pr.ny, pr.modes, dev)
+        u = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device=dev)
+        insts.append(dict(nx=pr.nx, ny=pr.ny, h=pr.h, tau=pr.tau, c=pr.c, scheme=pr.scheme, steps=pr.steps,
+                          flags=0, u0=U0, v0=V0, u=u, lo=torch.empty_like(u), d=torch.empty_like(u)))
+    bt = w.wave2d_batch_create(insts)
+    try:
+        w.wave2d_batch_run(bt)
+        torch.cuda.synchronize()
+        ref = [[t[k].clone() for k in ("u", "lo", "d")] for t in insts]
+        for run in range(10):
+            for t in insts:
+                for k in ("u", "lo", "d"):
+                    t[k].fill_(float("nan"))
+            w.wave2d_batch_run(bt)
+            torch.cuda.synchronize()
+            for i, (t, r) in enumerate(zip(insts, ref)):
+                assert all(torch.equal(t[k], x) for k, x in zip(("u", "lo", "d"), r)), (run, i)
+            print(f"full batch run {run}: bitwise equal", flush=True)
+    finally:
+        w.wave2d_batch_destroy(bt)
