@@ -943,7 +943,7 @@ int wave2d_set_tuning(int precision, int scheme, const wave2d_tuning* t)
     if (si < 0) return fail(WAVE2D_EINVAL, "unknown scheme %d", scheme);
     if (t) {
         if (!stream_depth_supported(t->depth)) return fail(WAVE2D_EINVAL, "unsupported depth %d", t->depth);
-        if (t->rows < 8) return fail(WAVE2D_EINVAL, "rows must be >= 8");
+        if (t->rows < 1) return fail(WAVE2D_EINVAL, "rows must be >= 1");
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[precision][si].set = (t != nullptr);

@@ -714,6 +714,10 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
     // Candidate shapes: every supported depth whose interior kernel keeps
     // its state in registers, with fixed segment heights plus the heights
     // at which the work items fill k/2 rounds of the resident wave slots.
+    // Grids too small to fill the slots at 8-row segments also try 2 and 4
+    // rows: there a pass lasts as long as one item, and a shorter segment
+    // shortens the item (257^2 5-point FP64, 400 levels: 1.22 ms at depth 8
+    // and 8 rows, 0.99 ms at 2 rows).
     static const int depths[] = {1, 2, 3, 4, 6, 8};
     static const int rows_fixed[] = {8, 16, 24, 32, 48, 64};
     W2D_HIP(hipEventCreate(&e0));
@@ -758,6 +762,10 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
         if (fit.spills || fit.slots < 1 || fit.strip_cols < 1) continue;
         const int64_t nstrips = (nx + fit.strip_cols - 1) / fit.strip_cols;
         std::vector<int> rows_c(std::begin(rows_fixed), std::end(rows_fixed));
+        if (nstrips * ((ny + 7) / 8) < fit.slots) {
+            rows_c.push_back(2);
+            rows_c.push_back(4);
+        }
         for (int k = 2; k <= 16; ++k) {
             const int64_t segs = (int64_t)k * fit.slots / (2 * nstrips);
             if (segs < 1) continue;

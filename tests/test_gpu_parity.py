@@ -143,6 +143,41 @@ def test_stream_f32c_bitwise_equals_simple(scheme, depth, rows):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("scheme", [w.P5, w.P9, w.P13])
+@pytest.mark.parametrize("depth", [2, 4, 8])
+def test_stream_bitwise_short_segments(scheme, depth):
+    # Segments of 1, 2 and 4 rows (shorter than a pass's reach): every
+    # item streams more halo rows than it outputs.
+    try:
+        _short_segments(scheme, depth)
+    finally:
+        w.wave2d_set_tuning(w.F64, scheme)
+        w.wave2d_set_tuning(w.F32C, scheme)
+
+
+def _short_segments(scheme, depth):
+    for (nx, ny) in [(263, 157), (257, 257), (40, 9)]:
+        u0, v0 = rough_data(nx, ny, nx + 7 * ny)
+        h = 1.0 / (max(nx, ny) - 1)
+        tau = _lam(scheme) * h
+        U0, V0 = dev_grid(u0), dev_grid(v0)
+        for rows in (1, 2, 4):
+            outs = []
+            for simple in (True, False):
+                if not simple:
+                    w.wave2d_set_tuning(w.F64, scheme, depth, rows)
+                    w.wave2d_set_tuning(w.F32C, scheme, depth, rows)
+                f = w.KERNEL_SIMPLE if simple else 0
+                UP, UC = torch.empty_like(U0), torch.empty_like(U0)
+                w.wave2d_run(U0, V0, UP, UC, h, tau, 1.0, scheme, 2 * depth + 3, f)
+                u = torch.empty(U0.shape, dtype=torch.float32, device=U0.device)
+                lo, d = torch.empty_like(u), torch.empty_like(u)
+                w.wave2d_f32c_run(U0, V0, u, lo, d, h, tau, 1.0, scheme, 2 * depth + 3, f)
+                outs.append([x.clone() for x in (UP, UC, u, lo, d)])
+            for a, b in zip(outs[0], outs[1]):
+                assert torch.equal(a, b), (nx, ny, rows)
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
 def test_stream_bitwise_random_shapes(seed):
     # Random grids (odd and even widths, both boundary rules, padded rows),

@@ -147,8 +147,11 @@ def test_tuning_roundtrip(L):
     assert L.wave2d_set_tuning(1, 9, None) == 0
     bad = _lib.Tuning(5, 40)
     assert L.wave2d_set_tuning(1, 9, ctypes.byref(bad)) == -1
-    bad = _lib.Tuning(2, 4)
+    bad = _lib.Tuning(2, 0)
     assert L.wave2d_set_tuning(1, 9, ctypes.byref(bad)) == -1
+    short = _lib.Tuning(2, 4)  # short segments are allowed (tiny grids)
+    assert L.wave2d_set_tuning(1, 9, ctypes.byref(short)) == 0
+    assert L.wave2d_set_tuning(1, 9, None) == 0
 
 
 def test_tune_cache_file_is_loaded(tmp_path):
