@@ -796,7 +796,9 @@ int wave2d_autotune(int precision, int scheme, int64_t nx, int64_t ny, void* str
         }
     }
     W2D_HIP(hipStreamSynchronize(s));
-    set_tuning_entry(precision, scheme, bt);
+    // A pick of fewer than 8 rows only suits grids as small as this one: it
+    // is kept for this size alone.
+    if (bt.rows >= 8) set_tuning_entry(precision, scheme, bt);
     set_tuning_size_entry(precision, scheme, nx, ny, bt);
     save_tune_cache(precision, scheme, nx, ny, bt);
     *best = bt;
